@@ -1,0 +1,87 @@
+"""Seeded synthetic inputs shaped like the paper's test matrices.
+
+Shared by the tests, the benchmark and the smoke check, on both sides of every
+parity comparison.  This module holds none of the Cholesky QR arithmetic: it
+only draws Gaussian numbers and orthonormalises them with LAPACK's Householder
+QR (numpy.linalg.qr), which the method under test does not use.
+
+Recipe (Sec. 3.1, test matrices A := U Sigma V): U (m x n) and V (n x n) are the
+positive-diagonal Q factors of seeded standard-normal matrices, Sigma holds
+values log-spaced from 1 down to 1/kappa, and A = U diag(s) V^T in FP64.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def rng(*key: int) -> np.random.Generator:
+    """PCG64 generator seeded by SeedSequence(key)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+        [int(k) for k in key])))
+
+
+def orthonormal(g: np.random.Generator, m: int, n: int) -> np.ndarray:
+    """Positive-diagonal Q factor of an m x n standard-normal matrix."""
+    G = g.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
+def singular_values(n: int, kappa: float) -> np.ndarray:
+    """n values log-spaced from 1 down to 1/kappa."""
+    if n == 1:
+        return np.ones(1)
+    return np.logspace(0.0, -math.log10(kappa), n)
+
+
+def test_matrix(m: int, n: int, kappa: float, seed=(0,)) -> np.ndarray:
+    """A = U diag(s) V^T with cond_2(A) = kappa (Fortran order, FP64)."""
+    g = rng(*seed, m, n, int(round(math.log10(kappa) * 100)))
+    U = orthonormal(g, m, n)
+    V = orthonormal(g, n, n)
+    s = singular_values(n, kappa)
+    return np.asfortranarray((U * s) @ V.T)
+
+
+def growth_blocks(m: int, n0: int, p: int, nblocks: int, kappa_lo: float,
+                  kappa_hi: float, coupling: float = 1e-3, seed: int = 2):
+    """Inputs of an iterative basis-growth run.
+
+    Returns (A0, [W_1..W_nblocks], kappas).  A0 (m x n0) has kappa = 1e2.
+    Block k is U_k diag(s_k) V_k^T + coupling * [U_0 .. U_{k-1}] G_k, with
+    kappa_k log-uniform in [kappa_lo, kappa_hi] and G_k Gaussian: the second
+    term ties each block to the span of all earlier blocks, so new columns are
+    nearly dependent on the basis grown so far.
+    """
+    g0 = rng(seed, 0, m, n0)
+    U0 = orthonormal(g0, m, n0)
+    V0 = orthonormal(g0, n0, n0)
+    A0 = np.asfortranarray((U0 * singular_values(n0, 1e2)) @ V0.T)
+    Us = [U0]
+    blocks, kappas = [], []
+    for k in range(1, nblocks + 1):
+        g = rng(seed, k, m, p)
+        lk = g.uniform(math.log10(kappa_lo), math.log10(kappa_hi))
+        kappa = 10.0 ** lk
+        Uk = orthonormal(g, m, p)
+        Vk = orthonormal(g, p, p)
+        prev = np.concatenate(Us, axis=1)
+        Gk = g.standard_normal((prev.shape[1], p))
+        W = (Uk * singular_values(p, kappa)) @ Vk.T + coupling * (prev @ Gk)
+        blocks.append(np.asfortranarray(W))
+        kappas.append(kappa)
+        Us.append(Uk)
+    return A0, blocks, kappas
+
+
+def hadamard(m: int) -> np.ndarray:
+    """Sylvester Hadamard matrix of order m (a power of two); H^T H = m I."""
+    assert m >= 1 and (m & (m - 1)) == 0
+    H = np.ones((1, 1))
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    return H

@@ -1,0 +1,432 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+closed forms (Hadamard constructions), brute force on tiny integer inputs,
+LAPACK / library special cases (Householder QR, potrf, trsm, eigvalsh), the
+invariants of Prop. 2.1 and the behaviour the paper reports.  The last group
+plants plausible mistakes in the oracle and checks that a pin catches each.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import cholqr as O
+import synth as S
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                     "paper_claims.json")))
+U = 2.0 ** -53
+
+
+def _householder_R(A):
+    """LAPACK Householder R with a positive diagonal (unique for full rank)."""
+    _, Rh = np.linalg.qr(A)
+    return np.sign(np.diag(Rh))[:, None] * Rh
+
+
+def _int_upper(g, n, lo=-3, hi=4, diag_pow=(0, 3)):
+    """Integer upper-triangular T with power-of-two diagonal."""
+    T = np.triu(g.integers(lo, hi, size=(n, n)).astype(np.float64), 1)
+    T += np.diag(2.0 ** g.integers(diag_pow[0], diag_pow[1] + 1, size=n))
+    return T
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+def test_gram_bruteforce_integers():
+    g = np.random.default_rng(1)
+    A = g.integers(-9, 10, size=(37, 6)).astype(np.float64)
+    X = O.gram(A)
+    for j in range(6):
+        for k in range(6):
+            exact = sum(int(A[i, j]) * int(A[i, k]) for i in range(37))
+            assert X[j, k] == exact
+
+
+def test_gram_hadamard_exact():
+    H = S.hadamard(256)[:, :40]
+    assert np.array_equal(O.gram(H), 256.0 * np.eye(40))
+
+
+def test_gram_append_and_schur_bruteforce():
+    g = np.random.default_rng(2)
+    Qi = g.integers(-4, 5, size=(23, 5)).astype(np.float64)
+    W = g.integers(-4, 5, size=(23, 3)).astype(np.float64)
+    Bt, G = O.gram_append(Qi, W)
+    X = O.schur(G, Bt)
+    for a in range(3):
+        for b in range(3):
+            gab = sum(int(W[i, a]) * int(W[i, b]) for i in range(23))
+            bb = sum(sum(int(Qi[i, c]) * int(W[i, a]) for i in range(23)) *
+                     sum(int(Qi[i, c]) * int(W[i, b]) for i in range(23))
+                     for c in range(5))
+            assert G[a, b] == gab
+            assert X[a, b] == gab - bb
+    for c in range(5):
+        for a in range(3):
+            assert Bt[c, a] == sum(int(Qi[i, c]) * int(W[i, a])
+                                   for i in range(23))
+
+
+def test_cholesky_exact_integer_factor():
+    g = np.random.default_rng(3)
+    for n in (1, 2, 5, 12):
+        T = _int_upper(g, n)
+        R, ok = O.cholesky_upper(T.T @ T)
+        assert ok
+        assert np.array_equal(R, T)
+
+
+def test_cholesky_matches_lapack_potrf():
+    g = np.random.default_rng(4)
+    for n in (3, 17, 64):
+        B = g.standard_normal((3 * n, n))
+        M = B.T @ B
+        R, ok = O.cholesky_upper(M)
+        assert ok
+        L = np.linalg.cholesky(M)
+        assert np.linalg.norm(R - L.T) <= 1e-13 * np.linalg.norm(L)
+        assert np.allclose(np.tril(R, -1), 0.0)
+
+
+@pytest.mark.parametrize("M", [
+    np.ones((2, 2)) + np.array([[0.0, 0.0], [0.0, 0.0]]),  # pivot exactly 0
+    np.array([[1.0, 2.0], [2.0, 1.0]]),                     # indefinite
+    np.array([[-1.0]]),                                     # negative pivot
+    np.zeros((3, 3)),                                       # zero matrix
+    np.array([[1.0, np.nan], [np.nan, 1.0]]),               # NaN off-diagonal
+    np.array([[np.inf, 0.0], [0.0, 1.0]]),                  # Inf pivot
+    np.array([[4.0, np.inf], [np.inf, 4.0]]),               # Inf off-diagonal
+])
+def test_cholesky_breakdown(M):
+    _, ok = O.cholesky_upper(M)
+    assert not ok
+
+
+def test_apply_inverse_exact():
+    g = np.random.default_rng(5)
+    T = _int_upper(g, 9)
+    Y = g.integers(-20, 21, size=(50, 9)).astype(np.float64)
+    assert np.array_equal(O.apply_inverse(Y @ T, T), Y)
+
+
+def test_apply_inverse_matches_trsm():
+    g = np.random.default_rng(6)
+    R = np.triu(g.standard_normal((20, 20))) + 5 * np.eye(20)
+    T = g.standard_normal((300, 20))
+    ref = scipy.linalg.solve_triangular(R, T.T, trans="T", lower=False).T
+    assert np.linalg.norm(O.apply_inverse(T, R) - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_lambda_max_exact_cases():
+    # c I: every start vector is an eigenvector; equal up to normalisation
+    # rounding (a few ulps)
+    assert abs(O.lambda_max(3.5 * np.eye(7)) - 3.5) <= 4 * U * 3.5
+    v = np.arange(1.0, 9.0)
+    lam = O.lambda_max(np.outer(v, v))
+    assert abs(lam - v @ v) <= 4 * U * (v @ v)
+    assert O.lambda_max(np.zeros((4, 4))) == 0.0
+
+
+def test_lambda_max_within_irlm_tolerance():
+    # Appendix A: the shift needs |lambda_max| only to tol 1e-2.  Gramians of
+    # the paper's test matrices (log-spaced singular values).
+    for n, kappa in ((5, 1e2), (20, 1e6), (100, 1e12), (256, 1e15)):
+        A = S.test_matrix(2 * n + 50, n, kappa, seed=(7,))
+        X = A.T @ A
+        ref = np.linalg.eigvalsh(X)[-1]
+        assert abs(O.lambda_max(X) - ref) <= 1e-2 * ref
+
+
+def test_lambda_max_is_lower_bound_on_clustered_spectrum():
+    # A Rayleigh quotient never exceeds lambda_max; with a clustered top of
+    # the spectrum (Wishart) 30 steps still land within 10 %.
+    g = np.random.default_rng(7)
+    for n in (5, 20, 100):
+        B = g.standard_normal((2 * n, n))
+        X = B.T @ B
+        ref = np.linalg.eigvalsh(X)[-1]
+        est = O.lambda_max(X)
+        assert 0.9 * ref <= est <= ref * (1 + 1e-13)
+
+
+def test_shift_formulas_exact():
+    # 11 (m n + n (n+1)) with m=1000, n=20 is 11 * 20420 = 224620; with
+    # ||X|| = 1 the shift is that integer times 2^-53, exactly.
+    assert O.shift_orth(1000, 20, 1.0) == math.ldexp(224620, -53)
+    # ||X|| = 4 scales by a power of two, exactly.
+    assert O.shift_orth(1000, 20, 4.0) == math.ldexp(224620, -51)
+    # floor 2u (Algorithm 1 shift step) when ||X|| = 0
+    assert O.shift_orth(1000, 20, 0.0) == 2 * U
+    # Algorithm 2 uses q: m=500, q=7 gives 11 (3500 + 56) = 39116.
+    assert O.shift_append_first(500, 7, 1.0) == math.ldexp(39116, -53)
+    # empty basis (q = 0): the formula gives 0, the floor gives 2u
+    assert O.shift_append_first(500, 0, 123.0) == 2 * U
+    assert GOLDEN["shift_constant"]["value"] == 11
+
+
+def test_metrics_exact():
+    H = S.hadamard(64)[:, :8]
+    Q = H / 8.0
+    assert O.loo(Q) == 0.0
+    R = 8.0 * np.eye(8)
+    assert O.rrr(H, Q, R) == 0.0
+    assert O.rcr(H, R) == 0.0
+
+
+# --------------------------------------------------------------------------
+# whole orth
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,kappa", [(200, 5, 1.0), (1000, 16, 1e2),
+                                       (2000, 32, 10.0), (64, 64, 1e2)])
+def test_orth_matches_householder(m, n, kappa):
+    A = S.test_matrix(m, n, kappa, seed=(10,))
+    Q, R, info = O.orth(A)
+    assert info["status"] == O.OK
+    Rh = _householder_R(A)
+    assert np.linalg.norm(R - Rh) <= 1e-12 * np.linalg.norm(Rh)
+    assert np.allclose(np.tril(R, -1), 0.0)
+
+
+@pytest.mark.parametrize("k,n", [(3, 8), (4, 16), (5, 32)])
+def test_orth_hadamard_closed_form(k, n):
+    """A = H T with H^T H = 4^k I: R = 2^k T and Q = H / 2^k, bit for bit."""
+    m = 4 ** k
+    H = S.hadamard(m)[:, :n]
+    T = _int_upper(np.random.default_rng(k), n)
+    A = H @ T
+    for kw in (dict(first_pass_shift=0, min_passes=0),   # Algorithm 1 as printed
+               dict(first_pass_shift=0, min_passes=3)):  # unshifted CholQR3
+        Q, R, info = O.orth(A, **kw)
+        assert info["status"] == O.OK
+        assert np.array_equal(R, (2.0 ** k) * T)
+        assert np.array_equal(Q, H / 2.0 ** k)
+        assert info["orth_fro"] == 0.0
+    _, _, info = O.orth(A, first_pass_shift=0, min_passes=0)
+    assert info["passes"] == 1
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e6, 1e10, 1e15])
+def test_orth_invariants_kappa_sweep(kappa):
+    A = S.test_matrix(3000, 16, kappa, seed=(11,))
+    Q, R, info = O.orth(A)
+    assert info["status"] == O.OK
+    assert O.loo(Q) <= 1e-12
+    assert O.rrr(A, Q, R) <= 1e-13
+    assert O.rcr(A, R) <= GOLDEN["fig2_rcr_upper"]["value"]
+    assert info["passes"] >= 3
+    assert info["sigma"][0] > 0.0
+
+
+def test_orth_first_pass_shift_value():
+    # CholQR3's first pass uses the paper's shift of the input Gramian.
+    A = S.test_matrix(5000, 12, 1e4, seed=(12,))
+    _, _, info = O.orth(A)
+    lam = np.linalg.eigvalsh(O.gram(A))[-1]
+    sig = 11.0 * (5000 * 12 + 12 * 13) * U * lam
+    assert abs(info["sigma"][0] - sig) <= 1e-2 * sig
+    assert info["sigma"][1] == 0.0 and info["sigma"][2] == 0.0
+
+
+def test_fig1_pattern_rscholqr_robust():
+    """Algorithm 1 as printed reaches the paper's stopping tolerance for
+    300 x 10 inputs up to kappa = 1e20, where the unshifted Gram breaks down."""
+    m, n = GOLDEN["fig1_shape"]["m"], GOLDEN["fig1_shape"]["n"]
+    tol = GOLDEN["stop_tol"]["value"]
+    broke = []
+    for e in range(0, 21, 2):
+        A = S.test_matrix(m, n, 10.0 ** e, seed=(6,))
+        Q, R, info = O.orth(A, first_pass_shift=0, min_passes=0)
+        assert info["status"] == O.OK, e
+        assert info["passes"] <= GOLDEN["max_iter"]["value"]
+        assert O.loo(Q) <= tol
+        assert O.rrr(A, Q, R) <= GOLDEN["fig2_rrr_upper"]["value"]
+        _, ok = O.cholesky_upper(O.gram(A))
+        broke.append(not ok)
+        if 10.0 ** e <= 1e4:
+            assert not broke[-1]
+    assert all(broke[6:])  # kappa >= 1e12: plain CholQR cannot even start
+
+
+def test_orth_nonfinite_and_not_converged():
+    A = S.test_matrix(400, 6, 1e2, seed=(13,))
+    A[17, 3] = np.nan
+    _, _, info = O.orth(A)
+    assert info["status"] == O.ENONFINITE
+    A = S.test_matrix(400, 6, 1e12, seed=(13,))
+    _, _, info = O.orth(A, max_iter=1, min_passes=0)
+    assert info["status"] == O.NOT_CONVERGED
+    assert info["passes"] == 1
+
+
+def test_orth_zero_column_not_converged():
+    # An exactly dependent column keeps a zero eigenvalue in every Gramian.
+    A = S.test_matrix(400, 6, 1e2, seed=(14,))
+    A[:, 2] = 0.0
+    _, _, info = O.orth(A)
+    assert info["status"] == O.NOT_CONVERGED
+    assert info["passes"] == 10
+
+
+# --------------------------------------------------------------------------
+# whole append (Prop. 2.1, Algorithm 2) and panel scheme (Algorithm 3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k,q,p", [(3, 8, 4), (4, 20, 10), (5, 60, 16)])
+def test_append_hadamard_closed_form(k, q, p):
+    """Q_in = H_q/2^k, W = H_p T + H_q C: B = 2^k C, R = 2^k T, Q = H_p/2^k."""
+    m = 4 ** k
+    H = S.hadamard(m)
+    Hq, Hp = H[:, :q], H[:, q:q + p]
+    g = np.random.default_rng(100 + k)
+    T = _int_upper(g, p)
+    C = g.integers(-3, 4, size=(q, p)).astype(np.float64)
+    Rin = _int_upper(g, q)
+    W = Hp @ T + Hq @ C
+    Qo, Ro, info = O.append(Hq / 2.0 ** k, Rin, W)
+    assert info["status"] == O.OK and info["passes"] == 1
+    assert info["sigma"] == [0.0]
+    assert np.array_equal(Qo[:, :q], Hq / 2.0 ** k)
+    assert np.array_equal(Qo[:, q:], Hp / 2.0 ** k)
+    assert np.array_equal(Ro[:q, :q], Rin)
+    assert np.array_equal(Ro[:q, q:], (2.0 ** k) * C)
+    assert np.array_equal(Ro[q:, q:], (2.0 ** k) * T)
+    assert np.array_equal(Ro[q:, :q], np.zeros((p, q)))
+
+
+def test_append_orthogonal_block_has_zero_B():
+    # Columns orthogonal to Q_in: B = Q_in^T A_in = 0 and X_jj = c_j^T c_j.
+    m, q, p = 256, 12, 5
+    H = S.hadamard(m)
+    W = H[:, q:q + p] * np.arange(1.0, p + 1)
+    Bt, G = O.gram_append(H[:, :q] / 16.0, W)
+    X = O.schur(G, Bt)
+    assert np.array_equal(np.diag(X), (W * W).sum(0))
+    _, Ro, info = O.append(H[:, :q] / 16.0, np.eye(q), W)
+    assert info["status"] == O.OK
+    assert np.array_equal(Ro[:q, q:], np.zeros((q, p)))
+
+
+def test_append_lucky_breakdown():
+    """W = Q_in b: X = 0 exactly, the shift is the 2u floor, the new block
+    stays zero and the update never converges."""
+    m, q, p = 256, 10, 3
+    Qin = S.hadamard(m)[:, :q] / 16.0
+    b = np.random.default_rng(9).integers(-3, 4, size=(q, p)).astype(float)
+    W = (16.0 * Qin) @ b
+    Bt, G = O.gram_append(Qin, W)
+    assert np.array_equal(O.schur(G, Bt), np.zeros((p, p)))
+    Qo, Ro, info = O.append(Qin, np.eye(q), W)
+    assert info["status"] == O.NOT_CONVERGED
+    assert info["sigma"][0] == 2 * U
+    assert np.array_equal(Qo[:, q:], np.zeros((m, p)))
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e8, 1e12])
+def test_append_prop21_identities(kappa):
+    A1 = S.test_matrix(4000, 12, 1e2, seed=(20,))
+    A2 = S.test_matrix(4000, 8, kappa, seed=(21,))
+    Q1, R1, _ = O.orth(A1)
+    Qo, Ro, info = O.append(Q1, R1, A2)
+    assert info["status"] == O.OK
+    Qn = Qo[:, 12:]
+    assert np.linalg.norm(Q1.T @ Qn) <= 1e-13
+    assert O.loo(Qn) <= 1e-13
+    assert O.loo(Qo) <= 1e-12
+    A = np.concatenate([A1, A2], axis=1)
+    assert O.rrr(A, Qo, Ro) <= 1e-13
+
+
+def test_append_equals_householder_of_concatenation():
+    A1 = S.test_matrix(3000, 10, 10.0, seed=(22,))
+    A2 = S.test_matrix(3000, 7, 1e2, seed=(23,))
+    Q1, R1, _ = O.orth(A1)
+    _, Ro, _ = O.append(Q1, R1, A2)
+    Rh = _householder_R(np.concatenate([A1, A2], axis=1))
+    assert np.linalg.norm(Ro - Rh) <= 1e-12 * np.linalg.norm(Rh)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5])
+def test_panel_scheme_matches_householder(r):
+    A = S.test_matrix(2000, 30, 1e2, seed=(24,))
+    Q, R, infos = O.panel(A, r)
+    assert all(i["status"] == O.OK for i in infos)
+    Rh = _householder_R(A)
+    assert np.linalg.norm(R - Rh) <= 1e-12 * np.linalg.norm(Rh)
+    assert O.loo(Q) <= 1e-12
+
+
+def test_panel_scheme_ill_conditioned():
+    A = S.test_matrix(2000, 20, 1e15, seed=(25,))
+    Q, R, infos = O.panel(A, 4)
+    assert all(i["status"] == O.OK for i in infos)
+    assert O.loo(Q) <= 1e-12
+    assert O.rrr(A, Q, R) <= 1e-13
+
+
+def test_growth_run_small():
+    A0, Ws, _ = S.growth_blocks(5000, 10, 10, 6, 1e2, 1e12)
+    Q, R, info = O.orth(A0)
+    assert info["status"] == O.OK
+    for W in Ws:
+        Q, R, info = O.append(Q, R, W)
+        assert info["status"] == O.OK
+    A = np.concatenate([A0] + Ws, axis=1)
+    assert O.loo(Q) <= 1e-12
+    assert O.rrr(A, Q, R) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# planted mistakes: each plausible slip in the oracle must fail a pin above
+# --------------------------------------------------------------------------
+def _fails(pin, *args):
+    try:
+        pin(*args)
+    except (AssertionError, ValueError, np.linalg.LinAlgError):
+        return True
+    return False
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    import oracle.cholqr as C
+    append_pin = lambda: test_append_hadamard_closed_form(4, 20, 10)
+    orth_pin = lambda: test_orth_hadamard_closed_form(4, 16)
+    hh_pin = lambda: test_orth_matches_householder(1000, 16, 1e2)
+    shift_pin = test_orth_first_pass_shift_value
+    for pin in (append_pin, orth_pin, hh_pin, shift_pin):
+        assert not _fails(pin)
+    mistakes = [
+        # Schur complement without the B~^T B~ term
+        ("schur", lambda G, Bt: G, append_pin),
+        # wrong sign of that term
+        ("schur", lambda G, Bt: G + Bt.T @ Bt, append_pin),
+        # B~ taken as W^T Q_in (transposed operand)
+        ("gram_append", lambda Qi, W: ((W.T @ Qi).T[::-1], C.gram(W)),
+         append_pin),
+        # transposed triangular factor in the apply
+        ("apply_inverse", (lambda f: lambda T, Rt: f(T, Rt.T))(C.apply_inverse),
+         orth_pin),
+        # forgetting the division by the diagonal in the substitution
+        ("apply_inverse", (lambda f: lambda T, Rt: f(T, Rt) * np.diag(Rt))(
+            C.apply_inverse), orth_pin),
+        # Gram of the rows instead of the columns (Q Q^T)
+        ("gram", lambda Q: (Q @ Q.T)[:Q.shape[1], :Q.shape[1]], hh_pin),
+        # ||X|| estimate off by a factor 100
+        ("lambda_max", (lambda f: lambda X, steps=30: f(X, steps) / 100.0)(
+            C.lambda_max), shift_pin),
+        # shift formula with n instead of n(n+1)
+        ("shift_orth", lambda m, n, x, u=U: max(11.0 * (m * n + n) * u * x,
+                                                2 * u), test_shift_formulas_exact),
+    ]
+    for name, bad, pin in mistakes:
+        with monkeypatch.context() as mp:
+            mp.setattr(C, name, bad)
+            assert _fails(pin), name
+    # missing square root on the Cholesky pivot
+    with monkeypatch.context() as mp:
+        mp.setattr(C.math, "sqrt", lambda x: x)
+        assert _fails(append_pin)
