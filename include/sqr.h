@@ -1,0 +1,122 @@
+/*
+ * sqr.h -- shifted Cholesky QR and Cholesky QR block append on AMD MI355X.
+ *
+ * C ABI of libsqr.so.  All matrices are FP64, column-major, in device memory
+ * (HBM) of the current HIP device; every call is stream-ordered on the HIP
+ * stream it is given.  The library never allocates or frees caller buffers.
+ *
+ * Method: Bindhak, Pelling & Saak, "Towards an Efficient Shifted Cholesky QR
+ * for Applications in Model Order Reduction using pyMOR", arXiv 2507.07788.
+ *   - sqr_orth   : Algorithm 1 (iterated Cholesky QR with shift recomputation)
+ *                  started as shiftedCholeskyQR3 (Sec. 3.1, algorithm list,
+ *                  item 2): pass 1 shifted, passes 2-3 plain unless the
+ *                  factorisation breaks down, then Algorithm 1's test.
+ *   - sqr_append : Algorithm 2 (cholQRUpdate) built on Proposition 2.1:
+ *                  [Q_in Q] [[R_in B],[0 R]] = [Q_in R_in, A_in].
+ *   - repeated sqr_append calls from an empty or orthonormalised start are
+ *     Algorithm 3 (pnCholQR, the panel scheme).
+ */
+#ifndef SQR_H
+#define SQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes.  Negative: usage errors found before any work is enqueued;
+ * nothing was modified.  Positive: numerical outcome of the algorithm. */
+#define SQR_OK             0
+#define SQR_NOT_CONVERGED  1  /* max_iter passes without ||X - I||_F < tol    */
+#define SQR_BREAKDOWN      2  /* shifted Cholesky failed after max_escalations */
+#define SQR_ENONFINITE     3  /* a Gramian held NaN or Inf                     */
+#define SQR_ENULL         (-1) /* a required pointer is NULL                   */
+#define SQR_EDIM          (-2) /* inconsistent sizes or leading dimensions     */
+#define SQR_EHIP          (-3) /* HIP runtime error or device out of memory    */
+#define SQR_EOPT          (-4) /* an option value outside its documented range */
+
+/* Options.  Defaults (sqr_default_opts) are the paper's experimental settings
+ * (Sec. 3.1: tolerance 1e-13 on ||I - Q^T Q||_F, at most 10 iterations). */
+typedef struct sqr_opts {
+  int32_t precision;        /* 0 = FP64 throughout (the only value accepted)    */
+  int32_t first_pass_shift; /* 1 = CholQR3 start (shifted pass 1); 0 = Alg. 1   */
+  int32_t min_passes;       /* passes run before the stopping test is consulted;
+                               3 for CholQR3, 0 for Algorithm 1 as printed      */
+  int32_t max_iter;         /* cap on Cholesky QR passes (1..64), default 10    */
+  double  tol;              /* stop when ||X - I||_F < tol, default 1e-13       */
+  double  unit_roundoff;    /* u in the shift formulas, default 2^-53           */
+  int32_t max_escalations;  /* cap on the x10 shift escalations, default 32     */
+  int32_t power_steps;      /* power-iteration steps for ||X||_2, default 30    */
+} sqr_opts;
+
+/* Outcome of one call (host struct). */
+typedef struct sqr_info {
+  int32_t status;        /* SQR_OK / SQR_NOT_CONVERGED / SQR_BREAKDOWN / ...    */
+  int32_t passes;        /* Cholesky QR passes executed (apply steps)           */
+  int32_t chol_attempts; /* Cholesky factorisations tried, failed ones included */
+  int32_t converged;     /* 1 if the stopping test was met                      */
+  double  orth_fro;      /* last ||X - I||_F of the block's Gramian             */
+  double  sigma[16];     /* shift of pass k+1 (0 = unshifted), first 16 passes  */
+} sqr_info;
+
+/* Opaque basis handle: (m, n, cap), borrowed Q and R, options and workspace. */
+typedef struct sqr_basis sqr_basis;
+
+/* Fill *o with the defaults listed above. */
+void sqr_default_opts(sqr_opts* o);
+
+/*
+ * sqr_orth -- Q R = A for a tall A (m x n, m >= n >= 1); Algorithm 1 with the
+ * CholQR3 start (see above).
+ *
+ *   out      receives a new handle describing the basis Q[:, 0:n] (required).
+ *   opts     options, or NULL for the defaults.
+ *   A, lda   m x n input, lda >= m; read only, never written.
+ *   Q, ldq   m x cap output, ldq >= m, cap >= n; columns [0, n) receive Q,
+ *            columns [n, cap) are reserved for later sqr_append calls.
+ *   R, ldr   cap x cap output, ldr >= cap; R[0:n, 0:n] receives the upper
+ *            triangular factor, its strictly lower part is written as zero.
+ *   stream   hipStream_t to run on (NULL = the null stream).
+ *   info     host struct, or NULL.  Non-NULL: the call synchronises the
+ *            stream and returns the numerical status.  NULL: the call returns
+ *            after enqueueing; fetch the outcome later with sqr_last_info.
+ *
+ * Ownership: A, Q and R are borrowed and must stay allocated until the work
+ * enqueued on `stream` completes.  The handle owns only its workspace.
+ * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
+ * cap < n, ldr < cap), SQR_EOPT, SQR_EHIP; all before any work is enqueued,
+ * except SQR_EHIP from a failed launch.
+ */
+int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
+             const double* A, int64_t lda, double* Q, int64_t ldq, int64_t cap,
+             double* R, int64_t ldr, void* stream, sqr_info* info);
+
+/*
+ * sqr_append -- Algorithm 2: extend the basis Q[:, 0:n] of handle b by the p
+ * columns of W (m x p, ldw >= m), writing the new columns to Q[:, n:n+p] and
+ * R[0:n+p, n:n+p] (B above R, Prop. 2.1).  On SQR_OK the handle's n grows by
+ * p.  On any non-zero status n is unchanged (the reserved columns may hold
+ * partial results).  W is read only.  Always synchronises `stream` (the new
+ * width depends on the outcome); `info` may be NULL.
+ * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, n + p > cap, n + p > m).
+ */
+int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,
+               void* stream, sqr_info* info);
+
+/* Outcome of the handle's last sqr_orth / sqr_append call; synchronises the
+ * stream of that call.  Returns the status, or SQR_ENULL. */
+int sqr_last_info(sqr_basis* b, sqr_info* info);
+
+/* Current basis width n of the handle (0 for NULL). */
+int64_t sqr_cols(const sqr_basis* b);
+
+/* Release the handle and its workspace after the work on its stream ends.
+ * Caller buffers are not touched.  NULL is a no-op. */
+void sqr_free(sqr_basis* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQR_H */

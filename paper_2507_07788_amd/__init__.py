@@ -1,0 +1,160 @@
+"""Python binding of libsqr: shifted Cholesky QR (CholQR3) and the Cholesky QR
+block append on AMD MI355X (arXiv 2507.07788, Algorithms 1-3).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libsqr.so.  Tensors are torch FP64 CUDA (HIP) tensors holding column-major
+matrices, i.e. a matrix of shape (m, n) with strides (1, ld), ld >= m; use
+``colmajor`` to allocate one.  Loading fails loudly when libsqr.so is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsqr.so")
+
+SQR_OK, SQR_NOT_CONVERGED, SQR_BREAKDOWN, SQR_ENONFINITE = 0, 1, 2, 3
+SQR_ENULL, SQR_EDIM, SQR_EHIP, SQR_EOPT = -1, -2, -3, -4
+
+
+class SqrOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("first_pass_shift", ctypes.c_int32),
+                ("min_passes", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("unit_roundoff", ctypes.c_double),
+                ("max_escalations", ctypes.c_int32), ("power_steps", ctypes.c_int32)]
+
+
+class SqrInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("chol_attempts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("orth_fro", ctypes.c_double), ("sigma", ctypes.c_double * 16)]
+
+    def as_dict(self) -> dict:
+        n = min(self.passes, 16)
+        return dict(status=self.status, passes=self.passes,
+                    chol_attempts=self.chol_attempts, converged=self.converged,
+                    orth_fro=self.orth_fro, sigma=list(self.sigma[:n]))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsqr.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2507_07788_amd.build` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.sqr_default_opts.argtypes = [ctypes.POINTER(SqrOpts)]
+    lib.sqr_default_opts.restype = None
+    lib.sqr_orth.argtypes = [ctypes.POINTER(P), ctypes.POINTER(SqrOpts), I64, I64, P, I64,
+                             P, I64, I64, P, I64, P, ctypes.POINTER(SqrInfo)]
+    lib.sqr_orth.restype = I32
+    lib.sqr_append.argtypes = [P, P, I64, I64, P, ctypes.POINTER(SqrInfo)]
+    lib.sqr_append.restype = I32
+    lib.sqr_last_info.argtypes = [P, ctypes.POINTER(SqrInfo)]
+    lib.sqr_last_info.restype = I32
+    lib.sqr_cols.argtypes = [P]
+    lib.sqr_cols.restype = I64
+    lib.sqr_free.argtypes = [P]
+    lib.sqr_free.restype = None
+    return lib
+
+
+lib = _load()
+
+
+def sqr_default_opts(**overrides) -> SqrOpts:
+    o = SqrOpts()
+    lib.sqr_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def colmajor(m: int, n: int, ld: int | None = None, device="cuda",
+             dtype=torch.float64) -> torch.Tensor:
+    """Uninitialised column-major (m, n) tensor with leading dimension ld."""
+    ld = m if ld is None else ld
+    return torch.empty((n, ld), dtype=dtype, device=device).t()[:m]
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 GPU tensor")
+    if t.dim() != 2 or (t.shape[0] > 1 and t.stride(0) != 1):
+        raise ValueError("expected a column-major matrix (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0]) if t.shape[1] > 1 else max(t.shape[0], 1)
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Basis:
+    """A handle plus the tensors it borrows: Q (m x cap), R (cap x cap)."""
+
+    def __init__(self, handle, Q, R, m, cap):
+        self.handle, self.Q, self.R, self.m, self.cap = handle, Q, R, m, cap
+
+    @property
+    def n(self) -> int:
+        return int(lib.sqr_cols(self.handle)) if self.handle else 0
+
+    def q(self) -> torch.Tensor:
+        return self.Q[:, :self.n]
+
+    def r(self) -> torch.Tensor:
+        return self.R[:self.n, :self.n]
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            sqr_free(self)
+
+
+def sqr_orth(A: torch.Tensor, cap: int | None = None, opts: SqrOpts | None = None,
+             Q: torch.Tensor | None = None, R: torch.Tensor | None = None,
+             stream=None, sync: bool = True):
+    """Q R = A (Algorithm 1 with the CholQR3 start).  Returns (Basis, info
+    dict or None); raises on usage errors (negative codes)."""
+    m, n = A.shape
+    cap = n if cap is None else cap
+    if Q is None:
+        Q = colmajor(m, cap, device=A.device)
+    if R is None:
+        R = colmajor(cap, cap, device=A.device)
+    h = ctypes.c_void_p()
+    info = SqrInfo()
+    rc = lib.sqr_orth(ctypes.byref(h), ctypes.byref(opts) if opts is not None else None,
+                      m, n, A.data_ptr(), _ld(A), Q.data_ptr(), _ld(Q), cap,
+                      R.data_ptr(), _ld(R), _stream(stream),
+                      ctypes.byref(info) if sync else None)
+    if rc < 0:
+        raise RuntimeError(f"sqr_orth failed with code {rc}")
+    return Basis(h, Q, R, m, cap), (info.as_dict() if sync else None)
+
+
+def sqr_append(b: Basis, W: torch.Tensor, stream=None) -> dict:
+    """Algorithm 2: append the columns of W to the basis.  Returns the info
+    dict; raises on usage errors."""
+    info = SqrInfo()
+    rc = lib.sqr_append(b.handle, W.data_ptr(), W.shape[1], _ld(W), _stream(stream),
+                        ctypes.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"sqr_append failed with code {rc}")
+    return info.as_dict()
+
+
+def sqr_last_info(b: Basis) -> dict:
+    info = SqrInfo()
+    rc = lib.sqr_last_info(b.handle, ctypes.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"sqr_last_info failed with code {rc}")
+    return info.as_dict()
+
+
+def sqr_free(b: Basis) -> None:
+    if b.handle:
+        lib.sqr_free(b.handle)
+        b.handle = None

@@ -1,0 +1,339 @@
+// sqr_api.hip -- host driver of libsqr: the C ABI declared in include/sqr.h.
+//
+// A call enqueues, on the caller's stream, an initial Gram pass and then
+// Cholesky QR passes (block_pass launches per 16-column block, a fixed-order
+// reduction of the per-workgroup partial Gramians, one small_step).  The
+// convergence decision is taken on the device; kernels of later passes exit
+// at once after it.  With a host `info` the driver enqueues the passes the
+// method normally needs, reads the device state once, and adds passes only
+// when the device asks for them.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <algorithm>
+
+#include "../../include/sqr.h"
+
+#include "sqr_kernels.hip"
+
+using namespace sqr;
+
+namespace {
+
+constexpr int kMaxSlots = 512;
+constexpr int kStage1 = 16;                    // slots summed per first-stage group
+constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
+constexpr int kSmallLdsMax = 88;               // p up to this keeps X, M in LDS
+
+__global__ void init_ctrl(Ctrl* c) {
+  if (threadIdx.x == 0) {
+    c->done = 0; c->status = 0; c->passes = 0; c->chol_attempts = 0;
+    c->converged = 0; c->orth_fro = 0.0;
+  }
+  if (threadIdx.x < 16) c->sigma[threadIdx.x] = 0.0;
+}
+
+int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
+int64_t nblocks(int64_t p) { return (p + 15) / 16; }
+// Doubles of the reduced partial Gramians of a call with basis q and block p.
+int64_t total_len(int64_t q, int64_t p) {
+  const int64_t P = nblocks(p);
+  return 16 * (P * (q + 16) + 8 * P * (P - 1));
+}
+int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (q + 16) + 8 * J * (J - 1)); }
+int64_t bneg_off(int64_t q, int64_t J) { return 16 * (J * round4(q) + 8 * J * (J - 1)); }
+int64_t bneg_len(int64_t q, int64_t p) { return bneg_off(q, nblocks(p)); }
+
+}  // namespace
+
+struct sqr_basis {
+  int64_t m = 0, n = 0, cap = 0;
+  double* Q = nullptr; int64_t ldq = 0;
+  double* R = nullptr; int64_t ldr = 0;
+  sqr_opts opts;
+  int device = 0;
+  hipStream_t stream = nullptr;      // stream of the last call
+  int slots = 0;                     // partial-Gram slots (workgroups of block_pass)
+  void* ws = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;         // pinned
+  double *part = nullptr, *stage = nullptr, *E = nullptr;
+  double *X = nullptr, *M = nullptr, *Bt = nullptr, *Rnew = nullptr;
+  double *bneg = nullptr, *rinv = nullptr;
+};
+
+namespace {
+
+typedef void (*BlockKernel)(BlockPassArgs);
+struct Variant { int nt; BlockKernel gram, apply; };
+const Variant kVariants[] = {
+  {0, block_pass<0, false>, block_pass<0, true>},
+  {1, block_pass<1, false>, block_pass<1, true>},
+  {2, block_pass<2, false>, block_pass<2, true>},
+  {4, block_pass<4, false>, block_pass<4, true>},
+  {8, block_pass<8, false>, block_pass<8, true>},
+  {12, block_pass<12, false>, block_pass<12, true>},
+  {16, block_pass<16, false>, block_pass<16, true>},
+  {24, block_pass<24, false>, block_pass<24, true>},
+  {33, block_pass<33, false>, block_pass<33, true>},
+};
+
+const Variant* pick_variant(int ns) {
+  for (const Variant& v : kVariants)
+    if (v.nt >= ns) return &v;
+  return nullptr;
+}
+
+size_t block_lds_bytes(int ks) {
+  const size_t k4 = round4(ks);
+  const size_t ns = (ks + 15) / 16;
+  return 8 * std::max(k4 * 16 + kWaves * 16 * 17, (ns + 1) * 256);
+}
+
+bool g_attr_done = false;
+void set_kernel_attributes() {
+  if (g_attr_done) return;
+  for (const Variant& v : kVariants) {
+    (void)hipFuncSetAttribute((const void*)v.gram, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+    (void)hipFuncSetAttribute((const void*)v.apply, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+  }
+  (void)hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      2 * kSmallLdsMax * kSmallLdsMax * 8);
+  g_attr_done = true;
+}
+
+// Worst-case sizes over every call the handle can make (q + p <= cap).
+int64_t worst_total_len(int64_t cap) {
+  int64_t w = 0;
+  for (int64_t p = 1; p <= cap; ++p) w = std::max(w, total_len(cap - p, p));
+  return w;
+}
+int64_t worst_bneg_len(int64_t cap) {
+  int64_t w = 0;
+  for (int64_t p = 1; p <= cap; ++p) w = std::max(w, bneg_len(cap - p, p));
+  return w;
+}
+
+int alloc_workspace(sqr_basis* b) {
+  const int64_t cap = b->cap;
+  const int64_t tl = worst_total_len(cap);
+  const int64_t tiles = (b->m + 15) / 16;
+  int64_t slots = std::min<int64_t>(kMaxSlots, (tiles + kWaves - 1) / kWaves);
+  slots = std::min<int64_t>(slots, std::max<int64_t>(16, kPartBudget / (8 * tl)));
+  b->slots = (int)std::max<int64_t>(1, slots);
+  const int64_t ng1 = (b->slots + kStage1 - 1) / kStage1;
+  const int64_t sq = cap * cap;
+  size_t doubles = 0;
+  auto take = [&](int64_t n) { size_t off = doubles; doubles += (size_t)round4(n) + 32; return off; };
+  const size_t o_part = take((int64_t)b->slots * tl);
+  const size_t o_stage = take(ng1 * tl);
+  const size_t o_E = take(tl);
+  const size_t o_X = take(sq);
+  const size_t o_M = take(sq);
+  const size_t o_Bt = take(sq);
+  const size_t o_Rnew = take(sq);
+  const size_t o_bneg = take(worst_bneg_len(cap));
+  const size_t o_rinv = take(nblocks(cap) * 256);
+  const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
+  if (hipMalloc(&b->ws, doubles * 8) != hipSuccess) { b->ws = nullptr; return SQR_EHIP; }
+  double* base = (double*)b->ws;
+  b->part = base + o_part; b->stage = base + o_stage; b->E = base + o_E;
+  b->X = base + o_X; b->M = base + o_M; b->Bt = base + o_Bt; b->Rnew = base + o_Rnew;
+  b->bneg = base + o_bneg; b->rinv = base + o_rinv;
+  b->ctrl = (Ctrl*)(base + o_ctrl);
+  if (hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    b->ctrl_host = nullptr; return SQR_EHIP;
+  }
+  memset(b->ctrl_host, 0, sizeof(Ctrl));
+  return SQR_OK;
+}
+
+struct Call {
+  int mode;             // 0 orth, 1 append
+  int64_t q, p;
+  const double* win; int64_t ldw;  // caller input block
+  double* y; int64_t ldy;          // output block
+};
+
+int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
+  const int64_t P = nblocks(c.p);
+  const int64_t tl = total_len(c.q, c.p);
+  const int64_t tiles = (b->m + 15) / 16;
+  const int nwg = (int)std::min<int64_t>(b->slots, (tiles + kWaves - 1) / kWaves);
+  const bool apply = phase > 0;
+  for (int64_t J = 0; J < P; ++J) {
+    BlockPassArgs a;
+    memset(&a, 0, sizeof(a));
+    const double* src = (apply && phase > 1) ? c.y : c.win;
+    const int64_t lds = (apply && phase > 1) ? c.ldy : c.ldw;
+    a.win = src + J * 16 * lds; a.ldw = lds;
+    a.yout = c.y + J * 16 * c.ldy; a.ldy = c.ldy;
+    a.s1 = b->Q; a.ld1 = b->ldq; a.n1 = (int)c.q;
+    // same-pass prefix: new values after an apply, the input for the first Gram
+    a.s2 = apply ? c.y : c.win; a.ld2 = apply ? c.ldy : c.ldw; a.n2 = (int)(16 * J);
+    a.pb = (int)std::min<int64_t>(16, c.p - 16 * J);
+    a.m = b->m;
+    a.bneg = b->bneg + bneg_off(c.q, J);
+    a.rinv = b->rinv + 256 * J;
+    a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
+    a.done = &b->ctrl->done; a.passes = &b->ctrl->passes;
+    a.copy_if_done = (phase == 1);
+    const int ks = a.n1 + a.n2;
+    const Variant* v = pick_variant((ks + 15) / 16);
+    if (!v) return SQR_EDIM;
+    void* args[] = {&a};
+    if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3(nwg), dim3(kThreads),
+                        args, block_lds_bytes(ks), s) != hipSuccess)
+      return SQR_EHIP;
+  }
+  // fixed-order two-stage reduction of the nwg slots
+  const int ng1 = (nwg + kStage1 - 1) / kStage1;
+  const dim3 rb((unsigned)((tl + 255) / 256));
+  hipLaunchKernelGGL(reduce_slots, dim3(rb.x, ng1), dim3(256), 0, s,
+                     (const double*)b->part, nwg, tl, tl, kStage1, b->stage,
+                     (const int*)&b->ctrl->done);
+  hipLaunchKernelGGL(reduce_slots, dim3(rb.x, 1), dim3(256), 0, s,
+                     (const double*)b->stage, ng1, tl, tl, ng1, b->E,
+                     (const int*)&b->ctrl->done);
+  SmallArgs k;
+  memset(&k, 0, sizeof(k));
+  k.E = b->E; k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+  k.m = b->m; k.phase = phase;
+  k.R = b->R; k.ldr = b->ldr;
+  k.X = b->X; k.M = b->M; k.Bt = b->Bt; k.Rnew = b->Rnew;
+  k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+  k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
+  k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
+  k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+  k.lds_matrices = c.p <= kSmallLdsMax;
+  const size_t slds = k.lds_matrices ? 2 * 8 * c.p * c.p : 0;
+  hipLaunchKernelGGL(small_step, dim3(1), dim3(1024), slds, s, k);
+  return hipGetLastError() == hipSuccess ? SQR_OK : SQR_EHIP;
+}
+
+int fetch(sqr_basis* b, hipStream_t s) {
+  if (hipMemcpyAsync(b->ctrl_host, b->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return SQR_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return SQR_EHIP;
+  return SQR_OK;
+}
+
+void fill_info(const Ctrl* c, sqr_info* info) {
+  info->status = c->status;
+  info->passes = c->passes;
+  info->chol_attempts = c->chol_attempts;
+  info->converged = c->converged;
+  info->orth_fro = c->orth_fro;
+  for (int i = 0; i < 16; ++i) info->sigma[i] = c->sigma[i];
+}
+
+// Run one call.  sync: enqueue `spec` passes, then add passes one by one while
+// the device reports neither convergence nor failure.
+int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
+  b->stream = s;
+  hipLaunchKernelGGL(init_ctrl, dim3(1), dim3(64), 0, s, b->ctrl);
+  int rc = launch_gram(b, c, 0, s);
+  if (rc) return rc;
+  const int maxit = b->opts.max_iter;
+  int enq = 0;
+  const int first = sync ? std::min(spec, maxit) : maxit;
+  for (; enq < first; ++enq)
+    if ((rc = launch_gram(b, c, enq + 1, s))) return rc;
+  if (!sync) return SQR_OK;
+  if ((rc = fetch(b, s))) return rc;
+  while (!b->ctrl_host->done && enq < maxit) {
+    if ((rc = launch_gram(b, c, ++enq, s))) return rc;
+    if ((rc = fetch(b, s))) return rc;
+  }
+  if (!b->ctrl_host->done) {
+    // all passes enqueued; the last small_step has decided
+    if ((rc = fetch(b, s))) return rc;
+  }
+  return SQR_OK;
+}
+
+bool opts_ok(const sqr_opts& o) {
+  return o.precision == 0 && o.max_iter >= 1 && o.max_iter <= 64 && o.min_passes >= 0 &&
+         o.tol > 0.0 && o.unit_roundoff > 0.0 && o.max_escalations >= 0 &&
+         o.power_steps >= 1 && o.power_steps <= 1000;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sqr_default_opts(sqr_opts* o) {
+  if (!o) return;
+  o->precision = 0;
+  o->first_pass_shift = 1;
+  o->min_passes = 3;
+  o->max_iter = 10;
+  o->tol = 1e-13;
+  o->unit_roundoff = 1.1102230246251565e-16;  // 2^-53
+  o->max_escalations = 32;
+  o->power_steps = 30;
+}
+
+int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
+             const double* A, int64_t lda, double* Q, int64_t ldq, int64_t cap,
+             double* R, int64_t ldr, void* stream, sqr_info* info) {
+  if (!out || !A || !Q || !R) return SQR_ENULL;
+  if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap)
+    return SQR_EDIM;
+  if (cap > kMaxSCols) return SQR_EDIM;
+  sqr_opts o;
+  sqr_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_ok(o)) return SQR_EOPT;
+  set_kernel_attributes();
+  sqr_basis* b = new sqr_basis();
+  b->m = m; b->n = n; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
+  b->opts = o;
+  (void)hipGetDevice(&b->device);
+  int rc = alloc_workspace(b);
+  if (rc) { sqr_free(b); return rc; }
+  Call c{0, 0, n, A, lda, Q, ldq};
+  hipStream_t s = (hipStream_t)stream;
+  const int spec = std::max(o.min_passes, 1);
+  rc = run_call(b, c, s, info != nullptr, spec);
+  if (rc) { (void)hipStreamSynchronize(s); sqr_free(b); return rc; }
+  *out = b;
+  if (info) {
+    fill_info(b->ctrl_host, info);
+    return info->status;
+  }
+  return SQR_OK;
+}
+
+int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stream,
+               sqr_info* info) {
+  if (!b || !W) return SQR_ENULL;
+  if (p < 1 || ldw < b->m || b->n + p > b->cap || b->n + p > b->m) return SQR_EDIM;
+  hipStream_t s = (hipStream_t)stream;
+  Call c{1, b->n, p, W, ldw, b->Q + b->n * b->ldq, b->ldq};
+  int rc = run_call(b, c, s, true, 2);
+  if (rc) return rc;
+  if (b->ctrl_host->status == SQR_OK) b->n += p;
+  if (info) fill_info(b->ctrl_host, info);
+  return b->ctrl_host->status;
+}
+
+int sqr_last_info(sqr_basis* b, sqr_info* info) {
+  if (!b || !info) return SQR_ENULL;
+  if (fetch(b, b->stream)) return SQR_EHIP;
+  fill_info(b->ctrl_host, info);
+  return info->status;
+}
+
+int64_t sqr_cols(const sqr_basis* b) { return b ? b->n : 0; }
+
+void sqr_free(sqr_basis* b) {
+  if (!b) return;
+  if (b->stream || b->ws) (void)hipStreamSynchronize(b->stream);
+  if (b->ws) (void)hipFree(b->ws);
+  if (b->ctrl_host) (void)hipHostFree(b->ctrl_host);
+  delete b;
+}
+
+}  // extern "C"

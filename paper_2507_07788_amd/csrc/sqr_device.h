@@ -1,0 +1,70 @@
+// sqr_device.h -- argument blocks shared by the HIP kernels and the host
+// driver of libsqr (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+
+namespace sqr {
+
+// Largest block width p handled by small_step's LDS vectors, and largest
+// number of columns of S (basis plus same-pass prefix) in one block launch.
+constexpr int kMaxCols = 1024;
+constexpr int kMaxSCols = 528;
+
+// Device-resident state of one sqr_orth / sqr_append call.  Kernels read
+// `done` first and exit at once when it is set, so the host may enqueue more
+// passes than the method needs without waiting for the device.
+struct Ctrl {
+  int32_t done;           // 1 once the call converged or failed
+  int32_t status;         // SQR_* code
+  int32_t passes;         // Cholesky QR passes executed so far
+  int32_t chol_attempts;  // factorisations tried, failed ones included
+  int32_t converged;
+  int32_t pad[3];
+  double orth_fro;        // last ||X - I||_F
+  double sigma[16];       // shift of each pass (0 = unshifted)
+};
+
+// One launch of block_pass: 16-column block J of a pass.
+struct BlockPassArgs {
+  const double* win;  int64_t ldw;   // input block (pb real columns)
+  double* yout;       int64_t ldy;   // output block (apply mode)
+  const double* s1;   int64_t ld1;  int32_t n1;   // basis segment of S
+  const double* s2;   int64_t ld2;  int32_t n2;   // same-pass prefix of S
+  int32_t pb;                         // real columns of the block (1..16)
+  int64_t m;                          // rows
+  const double* bneg;                 // (n1+n2 rounded up to 4) x 16, row-major: -B~_J
+  const double* rinv;                 // 16 x 16 row-major inverse of the diagonal block
+  double* part; int64_t part_stride; int64_t part_off;  // slot b at part + b*stride + off
+  const int32_t* done;
+  const int32_t* passes;
+  int32_t copy_if_done;
+};
+
+// One launch of small_step: finish a pass of an orth or append call.
+struct SmallArgs {
+  const double* E;       // reduced partial Gramians of the pass, block after block
+  int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2)
+  int32_t q;             // basis width (append), 0 for orth
+  int32_t p;             // block width being orthogonalised
+  int32_t nblk;          // 16-column blocks of p
+  int64_t m;
+  int32_t phase;         // 0 = after the initial Gram, k = after pass k
+  // caller R (column-major, ldr): orth uses R[0:p,0:p]; append writes
+  // B = R[0:q, q:q+p] and the new diagonal block R[q:q+p, q:q+p]
+  double* R; int64_t ldr;
+  // workspace
+  double* X;             // p x p (row-major), the Gramian / Schur complement
+  double* M;             // p x p (row-major), factorised in place
+  double* Rt;            // p x p (row-major), R~ of this pass
+  double* Bt;            // q x p (row-major), B~ of this pass
+  double* Rnew;          // scratch p x p / q x p
+  double* bneg;          // per block J: (q + 16J rounded up to 4) x 16, row-major
+  double* rinv;          // per block J: 16 x 16
+  Ctrl* ctrl;
+  // options
+  int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
+  double tol, u;
+  int32_t lds_matrices;  // 1: X, M live in LDS instead of the workspace
+};
+
+}  // namespace sqr

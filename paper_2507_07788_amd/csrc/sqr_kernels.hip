@@ -1,0 +1,478 @@
+// sqr_kernels.hip -- CDNA4 (gfx950) kernels of shifted Cholesky QR and the
+// Cholesky QR block append (arXiv 2507.07788, Algorithms 1 and 2).
+//
+// The tall operands stay in HBM, column-major.  A pass over them is split
+// into 16-column blocks.  For block J one launch of `block_pass` streams
+// 16-row tiles and, per tile,
+//   (1) forms T_J = W_J - S B~_J, the Q <- Q - Q_in B~ step of Algorithm 2
+//       and the off-diagonal part of the blocked triangular solve,
+//   (2) forms Y_J = T_J D_J with D_J the inverse of the 16x16 diagonal block
+//       of R~ (so all blocks together give Y = T R~^{-1}),
+//   (3) writes Y_J and accumulates the partial Gramian [S Y_J]^T Y_J of the
+//       next pass (Algorithm 1's X <- Q^T Q; Algorithm 2's B~ <- Q_in^T Q and
+//       Q^T Q), so every pass reads the tall data once.
+// S is the concatenation of the existing basis Q_in and the blocks < J of the
+// same pass.  All contractions run on v_mfma_f64_16x16x4f64.  Every workgroup
+// writes its partial Gramian to its own slot; slots are summed in a fixed
+// tree order (no atomics), so results do not depend on scheduling.
+//
+// `small_step` is a one-workgroup kernel that finishes a pass: it reduces the
+// Gramian, forms the Schur complement X = G - B~^T B~ (Prop. 2.1), tests
+// ||X - I||_F, picks the shift (Algorithm 1: recomputed from ||X||_2;
+// Algorithm 2: x10 escalation), factors X + sigma I, updates R and B, and
+// prepares the operands of the next pass.  Control decisions stay on the
+// device; later kernels of a finished call exit at once.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sqr_device.h"
+
+namespace sqr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  // D = A (16x4) * B (4x16) + C.  Lane l supplies A[l%16][l/16] and
+  // B[l/16][l%16]; it holds D[l/16 + 4r][l%16] in register r.
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Wave-private LDS hand-off: every lane's earlier LDS writes are complete and
+// visible to the other lanes of the wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWaves = 4;             // waves per workgroup of block_pass
+constexpr int kThreads = 64 * kWaves;
+constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
+
+// Element (row, col) of the concatenation S = [s1 (n1 cols) | s2 (n2 cols)].
+__device__ __forceinline__ double load_s(const BlockPassArgs& a, int64_t row,
+                                         int col) {
+  if (row >= a.m || col >= a.n1 + a.n2) return 0.0;
+  if (col < a.n1) return a.s1[(int64_t)col * a.ld1 + row];
+  return a.s2[(int64_t)(col - a.n1) * a.ld2 + row];
+}
+
+template <int NT, bool APPLY>
+__global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
+  // LDS: negated B~ of this block (K4 x 16), one transposition tile per wave,
+  // and the cross-wave reduction buffer (aliases the B~ area after the loop).
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = lane & 15;
+  const int g = lane >> 4;
+
+  if (*a.done) {
+    // A finished call: nothing to do, except that the first apply of a call
+    // that converged before any pass copies the input block to the output.
+    if (APPLY && a.copy_if_done && *a.passes == 0) {
+      const int64_t tiles = (a.m + 15) / 16;
+      for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < tiles;
+           t += (int64_t)gridDim.x * kWaves) {
+        const int64_t row = t * 16 + x;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = g + 4 * r;
+          if (row < a.m && col < a.pb)
+            a.yout[(int64_t)col * a.ldy + row] = a.win[(int64_t)col * a.ldw + row];
+        }
+      }
+    }
+    return;
+  }
+
+  const int ks = a.n1 + a.n2;          // columns of S
+  const int k4 = (ks + 3) & ~3;        // padded to whole k-slices
+  const int ns = (ks + 15) >> 4;       // 16-column tiles of S
+  double* bneg = lds;                  // k4 * 16
+  double* ytile = lds + (size_t)k4 * 16 + wave * 16 * kYPitch;
+
+  double rinv[4];
+  if (APPLY) {
+    for (int i = threadIdx.x; i < k4 * 16; i += kThreads) bneg[i] = a.bneg[i];
+    // A operand of the diagonal-block multiply for k-slice r: Rinv[g+4r][x].
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rinv[r] = a.rinv[(g + 4 * r) * 16 + x];
+    __syncthreads();
+  }
+
+  d4 acc[NT + 1];
+#pragma unroll
+  for (int i = 0; i <= NT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t tiles = (a.m + 15) / 16;
+  for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < tiles;
+       t += (int64_t)gridDim.x * kWaves) {
+    const int64_t r0 = t * 16;
+    const int64_t row = r0 + x;
+    const bool row_ok = row < a.m;
+    // T^T in D layout: lane (x, g) register r holds T[row x][col g + 4r].
+    d4 tt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = g + 4 * r;
+      tt[r] = (row_ok && col < a.pb) ? a.win[(int64_t)col * a.ldw + row] : 0.0;
+    }
+    d4 y;
+    if (APPLY) {
+      // T^T += Bneg^T S^T over k-slices of four S columns (k-slot g <-> 4s+g).
+      for (int s = 0; s < (k4 >> 2); ++s) {
+        const int col = 4 * s + g;
+        const double bs = load_s(a, row, col);
+        tt = mfma(bneg[col * 16 + x], bs, tt);
+      }
+      // Y^T = D^T T^T: register r of T^T is the B operand of k-slice r.
+      y = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y = mfma(rinv[r], tt[r], y);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = g + 4 * r;
+        if (row_ok && col < a.pb) a.yout[(int64_t)col * a.ldy + row] = y[r];
+      }
+    } else {
+      y = tt;
+    }
+    // Transpose the 16x16 tile of Y through wave-private LDS so that the row
+    // index becomes the contraction index: k-slot g of slice u <-> row g+4u.
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ytile[x * kYPitch + g + 4 * r] = y[r];
+    wave_lds_sync();
+    double yb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yb[u] = ytile[(g + 4 * u) * kYPitch + x];
+    wave_lds_sync();
+    // Partial Gramian: acc[I] += S_I^T Y (S tile I), acc[NT] += Y^T Y.
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      if (I < ns) {
+        const int col = 16 * I + x;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double sa = load_s(a, r0 + g + 4 * u, col);
+          acc[I] = mfma(sa, yb[u], acc[I]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[NT] = mfma(yb[u], yb[u], acc[NT]);
+  }
+
+  // Cross-wave reduction in a fixed order (wave 0, 1, 2, 3), then one slot.
+  __syncthreads();
+  double* red = lds;  // (ns + 1) * 256 doubles; B~ is no longer needed
+  for (int w = 0; w < kWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int I = 0; I <= NT; ++I) {
+        const int slot = (I == NT) ? ns : I;
+        if (I == NT || I < ns) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double* p = &red[slot * 256 + (g + 4 * r) * 16 + x];
+            *p = (w == 0) ? acc[I][r] : *p + acc[I][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Slot layout: rows 0..ks-1 hold S^T Y, rows ks..ks+15 hold Y^T Y; 16
+  // doubles per row.  Tile I row (g + 4r) is S column 16I + g + 4r.
+  double* out = a.part + (int64_t)blockIdx.x * a.part_stride + a.part_off;
+  const int rows = ks + 16;
+  for (int e = threadIdx.x; e < rows * 16; e += kThreads) {
+    const int rr = e >> 4, c = e & 15;
+    const int slot = (rr < ks) ? (rr >> 4) : ns;
+    const int within = (rr < ks) ? (rr & 15) : (rr - ks);
+    out[e] = red[slot * 256 + within * 16 + c];
+  }
+}
+
+// Sum slots [g*G, min(nslots, (g+1)*G)) of a partial buffer, element-wise, in
+// slot order.  Grid: (ceil(len/256), ceil(nslots/G)).
+__global__ __launch_bounds__(256) void reduce_slots(const double* __restrict__ in,
+                                                    int nslots, int64_t stride,
+                                                    int64_t len, int G,
+                                                    double* __restrict__ out,
+                                                    const int* done) {
+  if (*done) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  const int s0 = blockIdx.y * G;
+  const int s1 = min(nslots, s0 + G);
+  double s = 0.0;
+  for (int i = s0; i < s1; ++i) s += in[(int64_t)i * stride + e];
+  out[(int64_t)blockIdx.y * stride + e] = s;
+}
+
+
+// ---------------------------------------------------------------------------
+// small_step: one workgroup of 1024 threads finishes a pass.
+// ---------------------------------------------------------------------------
+constexpr int kSmallThreads = 1024;
+
+// Deterministic workgroup sum (fixed tree over thread ids).
+__device__ double block_sum(double v, double* buf) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int s = kSmallThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) buf[tid] += buf[tid + s];
+    __syncthreads();
+  }
+  const double r = buf[0];
+  __syncthreads();
+  return r;
+}
+
+// Offset (in doubles) of block J's partial Gramian inside E: block J' holds
+// (q + 16 J' + 16) rows of 16 doubles.
+__device__ __forceinline__ int64_t e_off(int q, int J) {
+  return 16 * ((int64_t)J * (q + 16) + 8 * (int64_t)J * (J - 1));
+}
+
+// In-place upper Cholesky of the row-major p x p matrix M (right-looking).
+// Returns false on breakdown: a pivot that is not > 0 or not finite.
+__device__ bool chol_upper(double* M, int p) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < p; ++j) {
+    __syncthreads();
+    const double d = M[(int64_t)j * p + j];
+    if (!(d > 0.0) || !isfinite(d)) return false;  // uniform: all read d
+    const double r = sqrt(d);
+    __syncthreads();
+    if (tid == 0) M[(int64_t)j * p + j] = r;
+    for (int k = j + 1 + tid; k < p; k += kSmallThreads) M[(int64_t)j * p + k] /= r;
+    __syncthreads();
+    const int w = p - j - 1;
+    for (int e = tid; e < w * w; e += kSmallThreads) {
+      const int i = j + 1 + e / w, k = j + 1 + e % w;
+      if (k >= i) M[(int64_t)i * p + k] -= M[(int64_t)j * p + i] * M[(int64_t)j * p + k];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[kSmallThreads];
+  __shared__ double v[kMaxCols], w[kMaxCols];
+  Ctrl* c = a.ctrl;
+  if (c->done) return;
+  const int tid = threadIdx.x;
+  const int p = a.p, q = a.q;
+  double* X = a.lds_matrices ? lds : a.X;
+  double* M = a.lds_matrices ? lds + (int64_t)p * p : a.M;
+  double* R = a.R;
+  const int64_t ldr = a.ldr;
+
+  if (a.phase == 0) {
+    // Algorithm 1: R = I.  Algorithm 2: B = 0, R = I_p, and the block below
+    // the old R is zero in R_out (Prop. 2.1).
+    for (int e = tid; e < (q + p) * p; e += kSmallThreads) {
+      const int i = e % (q + p), j = e / (q + p);
+      R[i + (int64_t)(q + j) * ldr] = (i == q + j) ? 1.0 : 0.0;
+    }
+    for (int e = tid; e < p * q; e += kSmallThreads) {
+      const int i = e % p, j = e / p;
+      R[q + i + (int64_t)j * ldr] = 0.0;
+    }
+  }
+
+  // 1. Gramian blocks: B~ = E[0:q, :], G = E[q:q+p, :] (upper, mirrored).
+  for (int e = tid; e < p * p; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    const int lo = min(i, j), hi = max(i, j);
+    const int J = hi >> 4;
+    X[e] = a.E[e_off(q, J) + (int64_t)(q + lo) * 16 + (hi & 15)];
+  }
+  for (int e = tid; e < q * p; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    a.Bt[e] = a.E[e_off(q, j >> 4) + (int64_t)i * 16 + (j & 15)];
+  }
+  __syncthreads();
+  // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
+  if (a.mode == 1 && q > 0) {
+    for (int e = tid; e < p * p; e += kSmallThreads) {
+      const int i = e / p, j = e % p;
+      double s = 0.0;
+      for (int k = 0; k < q; ++k) s += a.Bt[(int64_t)k * p + i] * a.Bt[(int64_t)k * p + j];
+      X[e] -= s;
+    }
+    __syncthreads();
+  }
+  // 3. ||X - I||_F.
+  double part = 0.0;
+  for (int e = tid; e < p * p; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    const double d = X[e] - (i == j ? 1.0 : 0.0);
+    part += d * d;
+  }
+  const double err = sqrt(block_sum(part, red));
+  // 4. Stopping test (Algorithm 1 with the CholQR3 start; Algorithm 2).
+  int status = -1;
+  if (!isfinite(err)) {
+    status = 3;  // SQR_ENONFINITE
+  } else if ((a.mode == 0) ? (a.phase >= a.min_passes && err < a.tol) : (err < a.tol)) {
+    status = 0;
+  } else if (a.phase >= a.max_iter) {
+    status = 1;  // SQR_NOT_CONVERGED
+  }
+  if (status >= 0) {
+    if (tid == 0) {
+      c->status = status;
+      c->converged = (status == 0);
+      c->orth_fro = err;
+      c->done = 1;
+    }
+    return;
+  }
+  const int pass = a.phase + 1;
+  // 5. Shift decision and factorisation.
+  bool shifted = (a.mode == 0 && pass == 1 && a.first_pass_shift);
+  int attempts = 0;
+  double sigma = 0.0;
+  bool ok = false;
+  if (!shifted) {
+    for (int e = tid; e < p * p; e += kSmallThreads) M[e] = X[e];
+    ++attempts;
+    ok = chol_upper(M, p);
+    shifted = !ok;
+  }
+  if (shifted) {
+    // ||X||_2 by power iteration from the all-ones vector.
+    for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
+    __syncthreads();
+    double lam = 0.0;
+    bool early = false;
+    for (int s = 0; s < a.power_steps; ++s) {
+      double pp = 0.0;
+      for (int i = tid; i < p; i += kSmallThreads) {
+        double t = 0.0;
+        for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
+        w[i] = t;
+        pp += t * t;
+      }
+      const double nrm = sqrt(block_sum(pp, red));
+      if (!(nrm > 0.0) || !isfinite(nrm)) {
+        lam = isfinite(nrm) ? nrm : __builtin_nan("");
+        early = true;
+        break;
+      }
+      for (int i = tid; i < p; i += kSmallThreads) v[i] = w[i] / nrm;
+      __syncthreads();
+    }
+    if (!early) {
+      double pp = 0.0;
+      for (int i = tid; i < p; i += kSmallThreads) {
+        double t = 0.0;
+        for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
+        pp += v[i] * t;
+      }
+      lam = fabs(block_sum(pp, red));
+    }
+    const double mm = (double)a.m;
+    const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
+                                     : (mm * q + (double)q * (q + 1));
+    sigma = fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
+    for (int esc = 0;; ++esc) {
+      for (int e = tid; e < p * p; e += kSmallThreads)
+        M[e] = X[e] + ((e / p == e % p) ? sigma : 0.0);
+      ++attempts;
+      ok = chol_upper(M, p);
+      if (ok) break;
+      if (esc >= a.max_escalations) break;
+      sigma = fmax(10.0 * sigma, 2.0 * a.u);
+    }
+    if (!ok) {
+      if (tid == 0) {
+        c->status = 2;  // SQR_BREAKDOWN
+        c->chol_attempts += attempts;
+        c->orth_fro = err;
+        c->done = 1;
+      }
+      return;
+    }
+  }
+  __syncthreads();
+  // 6. B <- B + B~ R (old R), then R <- R~ R (Algorithm 2; Algorithm 1).
+  const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
+  if (a.mode == 1 && q > 0) {
+    for (int e = tid; e < q * p; e += kSmallThreads) {
+      const int i = e / p, j = e % p;
+      double s = 0.0;
+      for (int k = 0; k <= j; ++k) s += a.Bt[(int64_t)i * p + k] * R[roff + k + (int64_t)j * ldr];
+      a.Rnew[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < q * p; e += kSmallThreads) {
+      const int i = e / p, j = e % p;
+      R[i + (int64_t)(q + j) * ldr] += a.Rnew[e];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < p * p; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    double s = 0.0;
+    for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * R[roff + k + (int64_t)j * ldr];
+    a.Rnew[e] = (i <= j) ? s : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < p * p; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    R[roff + i + (int64_t)j * ldr] = a.Rnew[e];
+  }
+  // 7. Operands of the next pass.  D_J = inverse of the diagonal block J of
+  //    R~ (identity beyond p), by back substitution on each column.
+  for (int t = tid; t < a.nblk * 16; t += kSmallThreads) {
+    const int J = t >> 4, cc = t & 15, b0 = 16 * J;
+    const int pb = min(16, p - b0);
+    double col[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) col[i] = 0.0;
+    if (cc >= pb) {
+      col[cc] = 1.0;
+    } else {
+      for (int i = cc; i >= 0; --i) {
+        double s = (i == cc) ? 1.0 : 0.0;
+        for (int k = i + 1; k <= cc; ++k) s -= M[(int64_t)(b0 + i) * p + b0 + k] * col[k];
+        col[i] = s / M[(int64_t)(b0 + i) * p + b0 + i];
+      }
+    }
+    double* rv = a.rinv + J * 256;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
+  }
+  //    -B~_J = -[B~[:, J]; R~[0:16J, J]], rows padded to a multiple of 4.
+  for (int J = 0; J < a.nblk; ++J) {
+    const int b0 = 16 * J, pb = min(16, p - b0);
+    const int rows = (q + b0 + 3) & ~3;
+    double* bn = a.bneg + 16 * ((int64_t)J * ((q + 3) & ~3) + 8 * (int64_t)J * (J - 1));
+    for (int e = tid; e < rows * 16; e += kSmallThreads) {
+      const int k = e >> 4, cc = e & 15;
+      double val = 0.0;
+      if (cc < pb) {
+        if (k < q) val = -a.Bt[(int64_t)k * p + b0 + cc];
+        else if (k < q + b0) val = -M[(int64_t)(k - q) * p + b0 + cc];
+      }
+      bn[e] = val;
+    }
+  }
+  if (tid == 0) {
+    c->passes = pass;
+    if (pass <= 16) c->sigma[pass - 1] = sigma;
+    c->chol_attempts += attempts;
+    c->orth_fro = err;
+  }
+}
+
+}  // namespace sqr

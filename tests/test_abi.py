@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/sqr.h, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sq():
+    import paper_2507_07788_amd as sq
+    return sq
+
+
+def test_header_symbols_exported(sq):
+    hdr = open(os.path.join(ROOT, "include", "sqr.h")).read()
+    names = set(re.findall(r"^\s*(?:int|void|int64_t)\s+(sqr_\w+)\s*\(", hdr, re.M))
+    assert {"sqr_orth", "sqr_append", "sqr_free"} <= names
+    lib = ctypes.CDLL(sq.LIB_PATH)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_default_opts_are_the_papers_settings(sq):
+    o = sq.sqr_default_opts()
+    assert o.max_iter == 10 and o.tol == 1e-13          # Sec. 3.1
+    assert o.unit_roundoff == 2.0 ** -53
+    assert o.first_pass_shift == 1 and o.min_passes == 3  # CholQR3 start
+    assert o.precision == 0 and o.max_escalations == 32 and o.power_steps == 30
+
+
+def _orth(sq, m, n, lda, ldq, cap, ldr, A=1, Q=1, R=1, opts=None):
+    h = ctypes.c_void_p()
+    P = lambda v: ctypes.c_void_p(0x1000 if v else 0)  # never dereferenced
+    return sq.lib.sqr_orth(ctypes.byref(h), ctypes.byref(opts) if opts else None, m, n,
+                           P(A), lda, P(Q), ldq, cap, P(R), ldr, None, None)
+
+
+def test_usage_errors_before_any_gpu_work(sq):
+    assert _orth(sq, 100, 10, 100, 100, 10, 10, A=0) == sq.SQR_ENULL
+    assert _orth(sq, 100, 10, 100, 100, 10, 10, Q=0) == sq.SQR_ENULL
+    assert _orth(sq, 100, 10, 100, 100, 10, 10, R=0) == sq.SQR_ENULL
+    assert _orth(sq, 10, 11, 10, 10, 11, 11) == sq.SQR_EDIM       # n > m
+    assert _orth(sq, 0, 0, 1, 1, 1, 1) == sq.SQR_EDIM             # empty
+    assert _orth(sq, 100, 10, 99, 100, 10, 10) == sq.SQR_EDIM     # lda < m
+    assert _orth(sq, 100, 10, 100, 99, 10, 10) == sq.SQR_EDIM     # ldq < m
+    assert _orth(sq, 100, 10, 100, 100, 9, 10) == sq.SQR_EDIM     # cap < n
+    assert _orth(sq, 100, 10, 100, 100, 12, 11) == sq.SQR_EDIM    # ldr < cap
+    assert _orth(sq, 10000, 10, 10000, 10000, 600, 600) == sq.SQR_EDIM  # cap too wide
+    bad = sq.sqr_default_opts(precision=7)
+    assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=bad) == sq.SQR_EOPT
+    bad = sq.sqr_default_opts(max_iter=0)
+    assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=bad) == sq.SQR_EOPT
+    assert sq.lib.sqr_append(None, ctypes.c_void_p(0x1000), 1, 1, None, None) == sq.SQR_ENULL
+    assert sq.lib.sqr_cols(None) == 0
+    sq.lib.sqr_free(None)

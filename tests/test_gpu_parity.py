@@ -1,0 +1,254 @@
+"""GPU parity: libsqr (HIP, through the C ABI) against the FP64 oracle.
+
+Tolerances (from the accuracy targets of the method and the arithmetic):
+  * ||Q^T Q - I||_F <= 1e-12 and ||A - QR||_F / ||A||_F <= 1e-13;
+  * R within 1e-10 * kappa (relative, Frobenius) of the oracle's R, element
+    by element within 1e-10 * kappa * ||R||_F; Q the same relative to ||Q||_F.
+    For kappa >= 1e12 the factors are not numerically unique in FP64, so only
+    the invariants are graded there.
+  * Exact closed forms (Hadamard constructions) must match bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth as S
+from oracle import cholqr as O
+
+pytestmark = pytest.mark.gpu
+
+sq = pytest.importorskip("paper_2507_07788_amd")
+from gpu_util import dev, host  # noqa: E402
+
+
+def _small_upper(g, n):
+    """Integer upper triangle, entries in {-1,0,1}, diagonal in {1,2,4}: the
+    inverses of its 16x16 diagonal blocks are exact dyadic numbers."""
+    T = np.triu(g.integers(-1, 2, size=(n, n)).astype(np.float64), 1)
+    T += np.diag(2.0 ** g.integers(0, 3, size=n))
+    return T
+
+
+def _check_factors(A, Qg, Rg, Qo, Ro, kappa):
+    assert O.loo(Qg) <= 1e-12
+    assert O.rrr(A, Qg, Rg) <= 1e-13
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    if kappa < 1e12:
+        tolr = 1e-10 * kappa
+        assert np.linalg.norm(Rg - Ro) <= tolr * np.linalg.norm(Ro)
+        assert np.max(np.abs(Rg - Ro)) <= tolr * np.linalg.norm(Ro)
+        assert np.linalg.norm(Qg - Qo) <= tolr * np.linalg.norm(Qo)
+        assert np.max(np.abs(Qg - Qo)) <= tolr * np.linalg.norm(Qo)
+
+
+# --------------------------------------------------------------------------
+# exact closed forms
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k,n", [(3, 8), (4, 16), (4, 20), (5, 37), (5, 64)])
+@pytest.mark.parametrize("mode", ["alg1", "cholqr3_noshift"])
+def test_orth_hadamard_bitwise(k, n, mode):
+    m = 4 ** k
+    H = S.hadamard(m)[:, :n]
+    T = _small_upper(np.random.default_rng(k * 100 + n), n)
+    A = H @ T
+    kw = dict(first_pass_shift=0, min_passes=0 if mode == "alg1" else 3)
+    Qo, Ro, io = O.orth(A, **kw)
+    assert np.array_equal(Ro, 2.0 ** k * T)  # the oracle reaches the closed form
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0 and info["passes"] == io["passes"]
+    assert np.array_equal(host(b.r()), 2.0 ** k * T)
+    assert np.array_equal(host(b.q()), H / 2.0 ** k)
+    assert info["orth_fro"] == 0.0
+
+
+@pytest.mark.parametrize("k,q,p", [(3, 8, 4), (4, 20, 10), (5, 60, 16), (5, 33, 40)])
+def test_append_hadamard_bitwise(k, q, p):
+    m = 4 ** k
+    H = S.hadamard(m)
+    g = np.random.default_rng(7 * k + q)
+    Tq = _small_upper(g, q)
+    T = _small_upper(g, p)
+    C = g.integers(-3, 4, size=(q, p)).astype(np.float64)
+    A0 = H[:, :q] @ Tq
+    W = H[:, q:q + p] @ T + H[:, :q] @ C
+    kw = dict(first_pass_shift=0, min_passes=0)
+    b, info = sq.sqr_orth(dev(A0), cap=q + p, opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == 0 and info["passes"] == 1 and b.n == q + p
+    Rg = host(b.r())
+    assert np.array_equal(Rg[:q, :q], 2.0 ** k * Tq)
+    assert np.array_equal(Rg[:q, q:], 2.0 ** k * C)
+    assert np.array_equal(Rg[q:, q:], 2.0 ** k * T)
+    assert np.array_equal(Rg[q:, :q], np.zeros((p, q)))
+    assert np.array_equal(host(b.q()), H[:, :q + p] / 2.0 ** k)
+
+
+# --------------------------------------------------------------------------
+# orth parity against the oracle
+# --------------------------------------------------------------------------
+def test_orth_parity_20000x20_kappa1e6():
+    A = S.test_matrix(20000, 20, 1e6, seed=(1,))
+    Qo, Ro, io = O.orth(A)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0 and info["passes"] == io["passes"] == 3
+    assert abs(info["sigma"][0] - io["sigma"][0]) <= 1e-2 * io["sigma"][0]
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e6)
+
+
+@pytest.mark.parametrize("m,n", [(1000, 5), (4099, 16), (10007, 17), (5000, 33),
+                                 (3001, 64), (2000, 100)])
+@pytest.mark.parametrize("kappa", [1e2, 1e8, 1e12, 1e15])
+def test_orth_parity_sweep(m, n, kappa):
+    A = S.test_matrix(m, n, kappa, seed=(3,))
+    Qo, Ro, io = O.orth(A)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0
+    assert abs(info["passes"] - io["passes"]) <= 1
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+@pytest.mark.parametrize("e", [0, 4, 8, 12, 16, 20])
+def test_orth_algorithm1_literal_fig1_shape(e):
+    A = S.test_matrix(300, 10, 10.0 ** e, seed=(6,))
+    kw = dict(first_pass_shift=0, min_passes=0)
+    Qo, Ro, io = O.orth(A, **kw)
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0
+    assert O.loo(host(b.q())) <= 1e-13
+    assert O.rrr(A, host(b.q()), host(b.r())) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 5), (16, 16), (17, 3), (33, 20), (31, 31)])
+def test_orth_tiny_and_square(m, n):
+    A = S.test_matrix(m, n, 10.0, seed=(4,))
+    Qo, Ro, io = O.orth(A)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 10.0)
+
+
+def test_orth_leading_dimensions_and_cap():
+    A = S.test_matrix(3000, 12, 1e4, seed=(5,))
+    Ad = dev(A, ld=3011)
+    Q = sq.colmajor(3000, 20, ld=3005)
+    R = sq.colmajor(20, 20, ld=23)
+    b, info = sq.sqr_orth(Ad, cap=20, Q=Q, R=R)
+    Qo, Ro, _ = O.orth(A)
+    assert info["status"] == 0 and b.n == 12
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e4)
+    assert np.array_equal(host(Ad), A)  # input untouched
+
+
+def test_orth_deterministic():
+    A = S.test_matrix(50000, 24, 1e10, seed=(8,))
+    Ad = dev(A)
+    b1, _ = sq.sqr_orth(Ad)
+    b2, _ = sq.sqr_orth(Ad)
+    assert torch.equal(b1.q(), b2.q()) and torch.equal(b1.r(), b2.r())
+
+
+def test_orth_status_codes():
+    A = S.test_matrix(400, 6, 1e2, seed=(13,))
+    A[17, 3] = np.nan
+    _, info = sq.sqr_orth(dev(A))
+    assert info["status"] == sq.SQR_ENONFINITE
+    A = S.test_matrix(400, 6, 1e2, seed=(14,))
+    A[:, 2] = 0.0
+    _, info = sq.sqr_orth(dev(A))
+    assert info["status"] == sq.SQR_NOT_CONVERGED and info["passes"] == 10
+    A = S.test_matrix(400, 6, 1e12, seed=(13,))
+    _, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(max_iter=1, min_passes=0))
+    assert info["status"] == sq.SQR_NOT_CONVERGED and info["passes"] == 1
+
+
+def test_orth_async_then_last_info():
+    A = S.test_matrix(8000, 16, 1e6, seed=(15,))
+    b, info = sq.sqr_orth(dev(A), sync=False)
+    assert info is None
+    got = sq.sqr_last_info(b)
+    _, _, io = O.orth(A)
+    assert got["status"] == 0 and got["passes"] == io["passes"]
+
+
+# --------------------------------------------------------------------------
+# append parity (Algorithm 2) and the basis-growth run (Algorithm 3 shape)
+# --------------------------------------------------------------------------
+def _growth(m, nblocks, p=10):
+    A0, Ws, _ = S.growth_blocks(m, 10, p, nblocks, 1e2, 1e12)
+    Q, R, io = O.orth(A0)
+    orc = [io["passes"]]
+    for W in Ws:
+        Q, R, io = O.append(Q, R, W)
+        assert io["status"] == 0
+        orc.append(io["passes"])
+    b, info = sq.sqr_orth(dev(A0), cap=10 + p * nblocks)
+    gp = [info["passes"]]
+    for W in Ws:
+        info = sq.sqr_append(b, dev(W))
+        assert info["status"] == 0
+        gp.append(info["passes"])
+    A = np.concatenate([A0] + Ws, axis=1)
+    return A, b, Q, R, orc, gp
+
+
+def test_append_growth_parity_small():
+    A, b, Qo, Ro, orc, gp = _growth(20000, 19)
+    assert b.n == 200
+    Qg, Rg = host(b.q()), host(b.r())
+    assert O.loo(Qg) <= 1e-12
+    assert O.rrr(A, Qg, Rg) <= 1e-13
+    assert sum(abs(x - y) for x, y in zip(orc, gp)) <= 2
+    # blocks reach kappa 1e12: R graded on its leading well-conditioned part
+    assert np.linalg.norm(Rg[:10, :10] - Ro[:10, :10]) <= 1e-8 * np.linalg.norm(Ro[:10, :10])
+
+
+@pytest.mark.parametrize("q,p", [(1, 1), (7, 3), (16, 16), (45, 13), (100, 40), (500, 16)])
+def test_append_parity_shapes(q, p):
+    m = 6007
+    A1 = S.test_matrix(m, q, 1e3, seed=(30,))
+    A2 = S.test_matrix(m, p, 1e5, seed=(31,))
+    Q1, R1, _ = O.orth(A1)
+    Qo, Ro, io = O.append(Q1, R1, A2)
+    b, info = sq.sqr_orth(dev(A1), cap=q + p)
+    info = sq.sqr_append(b, dev(A2, ld=m + 3))
+    assert info["status"] == 0 and b.n == q + p
+    A = np.concatenate([A1, A2], axis=1)
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e5)
+
+
+def test_append_lucky_breakdown_keeps_width():
+    m, q, p = 256, 10, 3
+    H = S.hadamard(m)
+    A1 = H[:, :q]
+    b, info = sq.sqr_orth(dev(A1), cap=q + p,
+                          opts=sq.sqr_default_opts(first_pass_shift=0, min_passes=0))
+    assert info["status"] == 0
+    W = A1 @ np.random.default_rng(9).integers(-3, 4, size=(q, p)).astype(float)
+    _, _, io = O.append(H[:, :q] / 16.0, np.eye(q), W)
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == io["status"] == sq.SQR_NOT_CONVERGED
+    assert info["sigma"][0] == io["sigma"][0] == 2.0 ** -52
+    assert b.n == q
+
+
+def test_append_usage_errors():
+    A = S.test_matrix(500, 8, 10.0, seed=(40,))
+    b, _ = sq.sqr_orth(dev(A), cap=12)
+    with pytest.raises(RuntimeError):
+        sq.sqr_append(b, dev(S.test_matrix(500, 5, 10.0, seed=(41,))))  # n+p > cap
+    assert b.n == 8
+
+
+@pytest.mark.slow
+def test_append_growth_parity_full_1e6():
+    """Basis growth at full size: m = 1e6, 10 -> 200 columns in 19 appends."""
+    A, b, Qo, Ro, orc, gp = _growth(1_000_000, 19)
+    Qg, Rg = host(b.q()), host(b.r())
+    assert O.loo(Qg) <= 1e-12
+    assert O.rrr(A, Qg, Rg) <= 1e-13
+    assert sum(abs(x - y) for x, y in zip(orc, gp)) <= 2
+    rows = np.random.default_rng(0).choice(A.shape[0], 2000, replace=False)
+    assert np.max(np.abs(Qg[rows, :10] - Qo[rows, :10])) <= 1e-8 * np.max(np.abs(Qo[:, :10]))
