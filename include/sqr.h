@@ -85,8 +85,8 @@ void sqr_default_opts(sqr_opts* o);
  * Ownership: A, Q and R are borrowed and must stay allocated until the work
  * enqueued on `stream` completes.  The handle owns only its workspace.
  * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
- * cap < n, ldr < cap), SQR_EOPT, SQR_EHIP; all before any work is enqueued,
- * except SQR_EHIP from a failed launch.
+ * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT, SQR_EHIP; all
+ * before any work is enqueued, except SQR_EHIP from a failed launch.
  */
 int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
              const double* A, int64_t lda, double* Q, int64_t ldq, int64_t cap,
@@ -99,7 +99,8 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
  * p.  On any non-zero status n is unchanged (the reserved columns may hold
  * partial results).  W is read only.  Always synchronises `stream` (the new
  * width depends on the outcome); `info` may be NULL.
- * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, n + p > cap, n + p > m).
+ * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^27, n + p > cap,
+ * n + p > m).
  */
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,
                void* stream, sqr_info* info);

@@ -39,6 +39,11 @@ class SqrInfo(ctypes.Structure):
                     orth_fro=self.orth_fro, sigma=list(self.sigma[:n]))
 
 
+class SqrProf(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 2), ("ms", ctypes.c_double * 2),
+                ("bytes", ctypes.c_double * 2)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libsqr.so is not built ({LIB_PATH}); run "
@@ -58,6 +63,10 @@ def _load():
     lib.sqr_cols.restype = I64
     lib.sqr_free.argtypes = [P]
     lib.sqr_free.restype = None
+    lib.sqr_prof_enable.argtypes = [I32]
+    lib.sqr_prof_enable.restype = None
+    lib.sqr_prof_read.argtypes = [ctypes.POINTER(SqrProf)]
+    lib.sqr_prof_read.restype = I32
     return lib
 
 
@@ -158,3 +167,18 @@ def sqr_free(b: Basis) -> None:
     if b.handle:
         lib.sqr_free(b.handle)
         b.handle = None
+
+
+def sqr_prof_enable(on: bool = True) -> None:
+    """Record HIP events around every streaming-kernel launch (sqr_prof.h)."""
+    lib.sqr_prof_enable(1 if on else 0)
+
+
+def sqr_prof_read() -> dict:
+    """Fold the recorded launches: {'gram'|'apply': (launches, ms, bytes)}."""
+    pr = SqrProf()
+    rc = lib.sqr_prof_read(ctypes.byref(pr))
+    if rc < 0:
+        raise RuntimeError(f"sqr_prof_read failed with code {rc}")
+    return {"gram": (pr.launches[0], pr.ms[0], pr.bytes[0]),
+            "apply": (pr.launches[1], pr.ms[1], pr.bytes[1])}

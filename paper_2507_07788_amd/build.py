@@ -10,6 +10,8 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs (no AGPR copies around each MFMA)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

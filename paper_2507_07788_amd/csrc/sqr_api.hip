@@ -12,8 +12,11 @@
 #include <stdint.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "../../include/sqr.h"
+#include "../../include/sqr_prof.h"
 
 #include "sqr_kernels.hip"
 
@@ -21,10 +24,44 @@ using namespace sqr;
 
 namespace {
 
-constexpr int kMaxSlots = 512;
+constexpr int kMaxSlots = 1024;
+// Leading dimensions up to this keep every per-lane buffer offset,
+// (3 ld + m) * 8 bytes, below 4 GiB.
+constexpr int64_t kMaxLd = (int64_t)1 << 27;
 constexpr int kStage1 = 16;                    // slots summed per first-stage group
 constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
 constexpr int kSmallLdsMax = 88;               // p up to this keeps X, M in LDS
+
+// ---- measurement records (sqr_prof.h) ----
+struct ProfRec { hipEvent_t e0, e1; int kind; double bytes; int64_t call; int phase; int real; };
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+bool g_prof_on = false;
+int64_t g_call_id = 0;
+
+hipEvent_t take_event() {
+  if (g_event_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = g_event_pool.back();
+  g_event_pool.pop_back();
+  return e;
+}
+
+// Mark the records of call `id`: launches of passes after the last executed
+// one were no-ops of a finished call.
+void prof_finalize(int64_t id, int passes) {
+  for (ProfRec& r : g_prof)
+    if (r.call == id && r.real < 0) r.real = (r.phase <= passes) ? 1 : 0;
+}
+
+// ---- single-entry workspace cache: a freed handle's device buffers are kept
+// for the next handle on the same device that fits in them ----
+std::mutex g_cache_mu;
+struct CachedWs { void* ptr = nullptr; size_t bytes = 0; int device = -1; void* pinned = nullptr; };
+CachedWs g_cache;
 
 __global__ void init_ctrl(Ctrl* c) {
   if (threadIdx.x == 0) {
@@ -39,9 +76,9 @@ int64_t nblocks(int64_t p) { return (p + 15) / 16; }
 // Doubles of the reduced partial Gramians of a call with basis q and block p.
 int64_t total_len(int64_t q, int64_t p) {
   const int64_t P = nblocks(p);
-  return 16 * (P * (q + 16) + 8 * P * (P - 1));
+  return 16 * (P * (round4(q) + 16) + 8 * P * (P - 1));
 }
-int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (q + 16) + 8 * J * (J - 1)); }
+int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (round4(q) + 16) + 8 * J * (J - 1)); }
 int64_t bneg_off(int64_t q, int64_t J) { return 16 * (J * round4(q) + 8 * J * (J - 1)); }
 int64_t bneg_len(int64_t q, int64_t p) { return bneg_off(q, nblocks(p)); }
 
@@ -54,6 +91,8 @@ struct sqr_basis {
   sqr_opts opts;
   int device = 0;
   hipStream_t stream = nullptr;      // stream of the last call
+  int64_t call_id = 0;               // id of the last call (measurement records)
+  size_t ws_bytes = 0;
   int slots = 0;                     // partial-Gram slots (workgroups of block_pass)
   void* ws = nullptr;
   Ctrl* ctrl = nullptr;
@@ -68,27 +107,27 @@ namespace {
 typedef void (*BlockKernel)(BlockPassArgs);
 struct Variant { int nt; BlockKernel gram, apply; };
 const Variant kVariants[] = {
-  {0, block_pass<0, false>, block_pass<0, true>},
   {1, block_pass<1, false>, block_pass<1, true>},
   {2, block_pass<2, false>, block_pass<2, true>},
+  {3, block_pass<3, false>, block_pass<3, true>},
   {4, block_pass<4, false>, block_pass<4, true>},
+  {5, block_pass<5, false>, block_pass<5, true>},
+  {6, block_pass<6, false>, block_pass<6, true>},
+  {7, block_pass<7, false>, block_pass<7, true>},
   {8, block_pass<8, false>, block_pass<8, true>},
-  {12, block_pass<12, false>, block_pass<12, true>},
-  {16, block_pass<16, false>, block_pass<16, true>},
-  {24, block_pass<24, false>, block_pass<24, true>},
-  {33, block_pass<33, false>, block_pass<33, true>},
+  {9, block_pass<9, false>, block_pass<9, true>},
 };
 
+// Variant by S tiles per wave (the four waves of a workgroup share them).
 const Variant* pick_variant(int ns) {
+  const int ntw = std::max(1, (ns + kWaveTiles - 1) / kWaveTiles);
   for (const Variant& v : kVariants)
-    if (v.nt >= ns) return &v;
+    if (v.nt >= ntw) return &v;
   return nullptr;
 }
 
-size_t block_lds_bytes(int ks) {
-  const size_t k4 = round4(ks);
-  const size_t ns = (ks + 15) / 16;
-  return 8 * std::max(k4 * 16 + kWaves * 16 * 17, (ns + 1) * 256);
+size_t block_lds_bytes() {
+  return 8 * ((size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch);
 }
 
 bool g_attr_done = false;
@@ -136,13 +175,25 @@ int alloc_workspace(sqr_basis* b) {
   const size_t o_bneg = take(worst_bneg_len(cap));
   const size_t o_rinv = take(nblocks(cap) * 256);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
-  if (hipMalloc(&b->ws, doubles * 8) != hipSuccess) { b->ws = nullptr; return SQR_EHIP; }
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cache.ptr && g_cache.device == b->device && g_cache.bytes >= doubles * 8) {
+      b->ws = g_cache.ptr; b->ws_bytes = g_cache.bytes;
+      b->ctrl_host = (Ctrl*)g_cache.pinned;
+      g_cache = CachedWs();
+    }
+  }
+  if (!b->ws) {
+    if (hipMalloc(&b->ws, doubles * 8) != hipSuccess) { b->ws = nullptr; return SQR_EHIP; }
+    b->ws_bytes = doubles * 8;
+  }
   double* base = (double*)b->ws;
   b->part = base + o_part; b->stage = base + o_stage; b->E = base + o_E;
   b->X = base + o_X; b->M = base + o_M; b->Bt = base + o_Bt; b->Rnew = base + o_Rnew;
   b->bneg = base + o_bneg; b->rinv = base + o_rinv;
   b->ctrl = (Ctrl*)(base + o_ctrl);
-  if (hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+  if (!b->ctrl_host &&
+      hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
     b->ctrl_host = nullptr; return SQR_EHIP;
   }
   memset(b->ctrl_host, 0, sizeof(Ctrl));
@@ -179,13 +230,25 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
     a.done = &b->ctrl->done; a.passes = &b->ctrl->passes;
     a.copy_if_done = (phase == 1);
-    const int ks = a.n1 + a.n2;
+    const int ks = (int)round4(a.n1) + a.n2;   // columns of S with the padding
     const Variant* v = pick_variant((ks + 15) / 16);
     if (!v) return SQR_EDIM;
     void* args[] = {&a};
+    ProfRec rec{};
+    if (g_prof_on) {
+      rec.e0 = take_event(); rec.e1 = take_event();
+      rec.kind = apply ? 1 : 0;
+      rec.bytes = 8.0 * (double)b->m * (double)(ks + (apply ? 2 : 1) * a.pb);
+      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
+      if (rec.e0) (void)hipEventRecord(rec.e0, s);
+    }
     if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3(nwg), dim3(kThreads),
-                        args, block_lds_bytes(ks), s) != hipSuccess)
+                        args, block_lds_bytes(), s) != hipSuccess)
       return SQR_EHIP;
+    if (g_prof_on && rec.e0 && rec.e1) {
+      (void)hipEventRecord(rec.e1, s);
+      g_prof.push_back(rec);
+    }
   }
   // fixed-order two-stage reduction of the nwg slots
   const int ng1 = (nwg + kStage1 - 1) / kStage1;
@@ -232,6 +295,7 @@ void fill_info(const Ctrl* c, sqr_info* info) {
 // the device reports neither convergence nor failure.
 int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   b->stream = s;
+  b->call_id = ++g_call_id;
   hipLaunchKernelGGL(init_ctrl, dim3(1), dim3(64), 0, s, b->ctrl);
   int rc = launch_gram(b, c, 0, s);
   if (rc) return rc;
@@ -250,6 +314,7 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
     // all passes enqueued; the last small_step has decided
     if ((rc = fetch(b, s))) return rc;
   }
+  if (g_prof_on) prof_finalize(b->call_id, b->ctrl_host->passes);
   return SQR_OK;
 }
 
@@ -281,7 +346,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   if (!out || !A || !Q || !R) return SQR_ENULL;
   if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap)
     return SQR_EDIM;
-  if (cap > kMaxSCols) return SQR_EDIM;
+  if (cap > kMaxSCols || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
   sqr_opts o;
   sqr_default_opts(&o);
   if (opts) o = *opts;
@@ -309,7 +374,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stream,
                sqr_info* info) {
   if (!b || !W) return SQR_ENULL;
-  if (p < 1 || ldw < b->m || b->n + p > b->cap || b->n + p > b->m) return SQR_EDIM;
+  if (p < 1 || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m) return SQR_EDIM;
   hipStream_t s = (hipStream_t)stream;
   Call c{1, b->n, p, W, ldw, b->Q + b->n * b->ldq, b->ldq};
   int rc = run_call(b, c, s, true, 2);
@@ -322,6 +387,7 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stre
 int sqr_last_info(sqr_basis* b, sqr_info* info) {
   if (!b || !info) return SQR_ENULL;
   if (fetch(b, b->stream)) return SQR_EHIP;
+  if (g_prof_on) prof_finalize(b->call_id, b->ctrl_host->passes);
   fill_info(b->ctrl_host, info);
   return info->status;
 }
@@ -331,9 +397,47 @@ int64_t sqr_cols(const sqr_basis* b) { return b ? b->n : 0; }
 void sqr_free(sqr_basis* b) {
   if (!b) return;
   if (b->stream || b->ws) (void)hipStreamSynchronize(b->stream);
-  if (b->ws) (void)hipFree(b->ws);
-  if (b->ctrl_host) (void)hipHostFree(b->ctrl_host);
+  if (b->ws) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cache.ptr && g_cache.bytes >= b->ws_bytes) {
+      (void)hipFree(b->ws);
+      if (b->ctrl_host) (void)hipHostFree(b->ctrl_host);
+    } else {
+      if (g_cache.ptr) {
+        (void)hipFree(g_cache.ptr);
+        if (g_cache.pinned) (void)hipHostFree(g_cache.pinned);
+      }
+      g_cache.ptr = b->ws; g_cache.bytes = b->ws_bytes; g_cache.device = b->device;
+      g_cache.pinned = b->ctrl_host;
+    }
+  } else if (b->ctrl_host) {
+    (void)hipHostFree(b->ctrl_host);
+  }
   delete b;
+}
+
+void sqr_prof_enable(int on) {
+  for (ProfRec& r : g_prof) { g_event_pool.push_back(r.e0); g_event_pool.push_back(r.e1); }
+  g_prof.clear();
+  g_prof_on = on != 0;
+}
+
+int sqr_prof_read(sqr_prof* out) {
+  if (!out) return SQR_ENULL;
+  memset(out, 0, sizeof(*out));
+  int rc = SQR_OK;
+  for (ProfRec& r : g_prof) {
+    if (hipEventSynchronize(r.e1) != hipSuccess) { rc = SQR_EHIP; continue; }
+    if (r.real == 0) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) { rc = SQR_EHIP; continue; }
+    out->launches[r.kind] += 1;
+    out->ms[r.kind] += ms;
+    out->bytes[r.kind] += r.bytes;
+  }
+  for (ProfRec& r : g_prof) { g_event_pool.push_back(r.e0); g_event_pool.push_back(r.e1); }
+  g_prof.clear();
+  return rc;
 }
 
 }  // extern "C"

@@ -40,6 +40,14 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 // Wave-private LDS hand-off: every lane's earlier LDS writes are complete and
 // visible to the other lanes of the wave.
+// Buffer descriptor over `bytes` bytes from `base` (range-checked loads past
+// the end return zero).  Ranges above 4 GiB are clamped to the 32-bit limit;
+// every offset used with a descriptor stays below 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const uint32_t n = bytes <= 0 ? 0u : (bytes >= 0xffffffffLL ? 0xffffffffu : (uint32_t)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
@@ -51,31 +59,39 @@ constexpr int kWaves = 4;             // waves per workgroup of block_pass
 constexpr int kThreads = 64 * kWaves;
 constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
 
-// Element (row, col) of the concatenation S = [s1 (n1 cols) | s2 (n2 cols)].
-__device__ __forceinline__ double load_s(const BlockPassArgs& a, int64_t row,
-                                         int col) {
-  if (row >= a.m || col >= a.n1 + a.n2) return 0.0;
-  if (col < a.n1) return a.s1[(int64_t)col * a.ld1 + row];
-  return a.s2[(int64_t)(col - a.n1) * a.ld2 + row];
-}
+// S is the concatenation [s1 (n1 columns) | zero padding up to q4 = n1
+// rounded up to 4 | s2 (n2 columns, a multiple of 16)], so every k-slice of
+// four columns lies in a single segment.  ks = q4 + n2 columns in all.
+//
+// Work split: a workgroup of four waves processes one 16-row tile at a time.
+// The 16-column tiles of S are dealt out round-robin (tile I -> wave I % 4),
+// so each wave keeps only its share of S, of -B~ and of the Gram
+// accumulators in registers.  The waves' partial sums of S B~ meet in LDS
+// (fixed order), every wave forms the same Y tile, and each wave then adds
+// S_I^T Y for its own tiles I.  Wave 0 owns the block input, the Y store and
+// Y^T Y.
+constexpr int kWaveTiles = 4;  // waves sharing the S tiles of a row tile
+constexpr int kTPart = 256;    // doubles per partial 16x16 tile in LDS
 
-template <int NT, bool APPLY>
+template <int NTW, bool APPLY>
 __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
-  // LDS: negated B~ of this block (K4 x 16), one transposition tile per wave,
-  // and the cross-wave reduction buffer (aliases the B~ area after the loop).
+  // LDS: double-buffered partial T tiles (2 x 4 x 256 doubles), then one
+  // 16x17 transposition tile per wave.
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int x = lane & 15;
   const int g = lane >> 4;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;   // row tiles per workgroup
+  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t t1 = min(tiles, t0 + per);
 
   if (*a.done) {
     // A finished call: nothing to do, except that the first apply of a call
     // that converged before any pass copies the input block to the output.
     if (APPLY && a.copy_if_done && *a.passes == 0) {
-      const int64_t tiles = (a.m + 15) / 16;
-      for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < tiles;
-           t += (int64_t)gridDim.x * kWaves) {
+      for (int64_t t = t0 + wave; t < t1; t += kWaves) {
         const int64_t row = t * 16 + x;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -88,111 +104,177 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     return;
   }
 
-  const int ks = a.n1 + a.n2;          // columns of S
-  const int k4 = (ks + 3) & ~3;        // padded to whole k-slices
+  const int q4 = (a.n1 + 3) & ~3;      // basis segment padded to whole k-slices
+  const int ks = q4 + a.n2;            // columns of S (a multiple of 4)
+  const int nk = ks >> 2;              // k-slices of four S columns
   const int ns = (ks + 15) >> 4;       // 16-column tiles of S
-  double* bneg = lds;                  // k4 * 16
-  double* ytile = lds + (size_t)k4 * 16 + wave * 16 * kYPitch;
+  double* tpart = lds;                                   // [2][4][256]
+  double* tr = lds + 2 * kWaves * kTPart + wave * 16 * kYPitch;
+  const int hi1 = a.n1 - 1, hi2 = a.n2 - 1;              // last column of each S segment
 
+  // A operands: -B~ rows of my k-slices (zero past the end of S) and the
+  // inverse diagonal block (k-slice r: Rinv[g+4r][x]).
+  double bn[NTW][4];
   double rinv[4];
   if (APPLY) {
-    for (int i = threadIdx.x; i < k4 * 16; i += kThreads) bneg[i] = a.bneg[i];
-    // A operand of the diagonal-block multiply for k-slice r: Rinv[g+4r][x].
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int s = 4 * (wave + kWaveTiles * j) + jj;
+        bn[j][jj] = (s < nk) ? a.bneg[(4 * s + g) * 16 + x] : 0.0;
+      }
 #pragma unroll
     for (int r = 0; r < 4; ++r) rinv[r] = a.rinv[(g + 4 * r) * 16 + x];
-    __syncthreads();
   }
 
-  d4 acc[NT + 1];
+  d4 acc[NTW];
 #pragma unroll
-  for (int i = 0; i <= NT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NTW; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  d4 accg = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t tiles = (a.m + 15) / 16;
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < tiles;
-       t += (int64_t)gridDim.x * kWaves) {
-    const int64_t r0 = t * 16;
-    const int64_t row = r0 + x;
+  // Loads of one row tile: my S slices and the block input.
+  auto load_tile = [&](int64_t tl, double (&sreg)[NTW][4], d4& w) {
+    const int64_t row = tl * 16 + x;
     const bool row_ok = row < a.m;
-    // T^T in D layout: lane (x, g) register r holds T[row x][col g + 4r].
-    d4 tt;
+    const int64_t rowc = row_ok ? row : a.m - 1;
+    {
+      // One buffer descriptor per slice: base at the slice's first column,
+      // range = bytes up to the end of the segment's last column, so columns
+      // past a segment (padding, slices past the end of S) read zero in
+      // hardware.  A lane adds only its own offset (g ld + row) * 8.
+      const uint32_t o1 = (uint32_t)(((int64_t)g * a.ld1 + rowc) * 8);
+      const uint32_t o2 = (uint32_t)(((int64_t)g * a.ld2 + rowc) * 8);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int col = g + 4 * r;
-      tt[r] = (row_ok && col < a.pb) ? a.win[(int64_t)col * a.ldw + row] : 0.0;
+      for (int j = 0; j < NTW; ++j)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int s = 4 * (wave + kWaveTiles * j) + jj;
+          const bool first = (4 * s < q4) || a.n2 == 0;
+          const int cs = first ? 4 * s : 4 * s - q4;
+          const int hi = first ? hi1 : hi2;
+          const int64_t ld = first ? a.ld1 : a.ld2;
+          const double* base = (first ? a.s1 : a.s2) + (int64_t)cs * ld;
+          const int64_t nrec = (hi >= cs) ? (((int64_t)(hi - cs) * ld + a.m) * 8) : 0;
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, nrec);
+          sreg[j][jj] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+              rs, (int)(first ? o1 : o2), 0, 0));
+        }
     }
+    // Block input in D layout: lane (x, g) register r holds W[row x][col g+4r].
+    // Columns past pb lie outside the buffer range and read zero; rows past
+    // m are cleared with a bit mask (values there may be anything).
+    {
+      const uint64_t keep = row_ok ? ~0ull : 0ull;
+      const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // columns 4r..4r+3 from base column 4r; lane offset (g ldw + row) * 8
+        const int64_t nrec = (a.pb - 1 >= 4 * r) ? (((int64_t)(a.pb - 1 - 4 * r) * a.ldw + a.m) * 8) : 0;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(4 * r) * a.ldw, nrec);
+        const uint64_t bits = __builtin_bit_cast(uint64_t,
+            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+        w[r] = __builtin_bit_cast(double, bits & keep);
+      }
+    }
+  };
+
+  double snext[NTW][4];
+  d4 wnext;
+  if (t0 < t1) load_tile(t0, snext, wnext);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t row = t * 16 + x;
+    const bool row_ok = row < a.m;
+    double sreg[NTW][4];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) sreg[j][jj] = snext[j][jj];
+    const d4 w = wnext;
+    // prefetch the next row tile (clamped to a valid tile)
+    load_tile(min(t + 1, t1 - 1), snext, wnext);
     d4 y;
     if (APPLY) {
-      // T^T += Bneg^T S^T over k-slices of four S columns (k-slot g <-> 4s+g).
-      for (int s = 0; s < (k4 >> 2); ++s) {
-        const int col = 4 * s + g;
-        const double bs = load_s(a, row, col);
-        tt = mfma(bneg[col * 16 + x], bs, tt);
-      }
+      // Partial T^T over my slices (two chains), wave 0 starts from W^T.
+      d4 c0 = (wave == 0) ? w : d4{0.0, 0.0, 0.0, 0.0};
+      d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < NTW; ++j)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj & 1) c1 = mfma(bn[j][jj], sreg[j][jj], c1);
+          else        c0 = mfma(bn[j][jj], sreg[j][jj], c0);
+        }
+      const d4 cp = c0 + c1;
+      double* tp = tpart + ((t & 1) * kWaves + wave) * kTPart;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = cp[r];
+      __syncthreads();
+      // T^T = sum of the partials in wave order.
+      d4 tt = d4{0.0, 0.0, 0.0, 0.0};
+      const double* tb = tpart + (t & 1) * kWaves * kTPart;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tt[r] += tb[v * kTPart + r * 64 + lane];
       // Y^T = D^T T^T: register r of T^T is the B operand of k-slice r.
       y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) y = mfma(rinv[r], tt[r], y);
+      if (!row_ok) y = d4{0.0, 0.0, 0.0, 0.0};
+      if (wave == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = g + 4 * r;
-        if (row_ok && col < a.pb) a.yout[(int64_t)col * a.ldy + row] = y[r];
+        for (int r = 0; r < 4; ++r) {
+          const int col = g + 4 * r;
+          if (row_ok && col < a.pb) a.yout[(int64_t)col * a.ldy + row] = y[r];
+        }
       }
     } else {
-      y = tt;
+      y = w;
     }
-    // Transpose the 16x16 tile of Y through wave-private LDS so that the row
-    // index becomes the contraction index: k-slot g of slice u <-> row g+4u.
+    // Y through wave-private LDS: the row index becomes the contraction index
+    // (k-slot g of slice u <-> row g + 4u).
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ytile[x * kYPitch + g + 4 * r] = y[r];
+    for (int r = 0; r < 4; ++r) tr[x * kYPitch + g + 4 * r] = y[r];
     wave_lds_sync();
     double yb[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) yb[u] = ytile[(g + 4 * u) * kYPitch + x];
+    for (int u = 0; u < 4; ++u) yb[u] = tr[(g + 4 * u) * kYPitch + x];
     wave_lds_sync();
-    // Partial Gramian: acc[I] += S_I^T Y (S tile I), acc[NT] += Y^T Y.
+    if (wave == 0) {
 #pragma unroll
-    for (int I = 0; I < NT; ++I) {
-      if (I < ns) {
-        const int col = 16 * I + x;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double sa = load_s(a, r0 + g + 4 * u, col);
-          acc[I] = mfma(sa, yb[u], acc[I]);
-        }
-      }
+      for (int u = 0; u < 4; ++u) accg = mfma(yb[u], yb[u], accg);
     }
+    // My S tiles through the same LDS tile: sreg[j][jj] = S[row x][16I + 4jj + g].
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[NT] = mfma(yb[u], yb[u], acc[NT]);
+    for (int j = 0; j < NTW; ++j) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) tr[x * kYPitch + 4 * jj + g] = sreg[j][jj];
+      wave_lds_sync();
+      double sa[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sa[u] = tr[(g + 4 * u) * kYPitch + x];
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[j] = mfma(sa[u], yb[u], acc[j]);
+    }
   }
 
-  // Cross-wave reduction in a fixed order (wave 0, 1, 2, 3), then one slot.
-  __syncthreads();
-  double* red = lds;  // (ns + 1) * 256 doubles; B~ is no longer needed
-  for (int w = 0; w < kWaves; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int I = 0; I <= NT; ++I) {
-        const int slot = (I == NT) ? ns : I;
-        if (I == NT || I < ns) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double* p = &red[slot * 256 + (g + 4 * r) * 16 + x];
-            *p = (w == 0) ? acc[I][r] : *p + acc[I][r];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // Slot layout: rows 0..ks-1 hold S^T Y, rows ks..ks+15 hold Y^T Y; 16
+  // Slot layout: rows 0..ks-1 hold S^T Y, rows ks..ks+15 hold Y^T Y, 16
   // doubles per row.  Tile I row (g + 4r) is S column 16I + g + 4r.
   double* out = a.part + (int64_t)blockIdx.x * a.part_stride + a.part_off;
-  const int rows = ks + 16;
-  for (int e = threadIdx.x; e < rows * 16; e += kThreads) {
-    const int rr = e >> 4, c = e & 15;
-    const int slot = (rr < ks) ? (rr >> 4) : ns;
-    const int within = (rr < ks) ? (rr & 15) : (rr - ks);
-    out[e] = red[slot * 256 + within * 16 + c];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int I = wave + kWaveTiles * j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 16 * I + g + 4 * r;
+      if (I < ns && rr < ks) out[rr * 16 + x] = acc[j][r];
+    }
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(ks + g + 4 * r) * 16 + x] = accg[r];
   }
 }
 
@@ -234,9 +316,10 @@ __device__ double block_sum(double v, double* buf) {
 }
 
 // Offset (in doubles) of block J's partial Gramian inside E: block J' holds
-// (q + 16 J' + 16) rows of 16 doubles.
-__device__ __forceinline__ int64_t e_off(int q, int J) {
-  return 16 * ((int64_t)J * (q + 16) + 8 * (int64_t)J * (J - 1));
+// (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4 (rows q..q4-1
+// belong to the zero padding of S and are ignored).
+__device__ __forceinline__ int64_t e_off(int q4, int J) {
+  return 16 * ((int64_t)J * (q4 + 16) + 8 * (int64_t)J * (J - 1));
 }
 
 // In-place upper Cholesky of the row-major p x p matrix M (right-looking).
@@ -289,15 +372,16 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   }
 
   // 1. Gramian blocks: B~ = E[0:q, :], G = E[q:q+p, :] (upper, mirrored).
+  const int q4 = (q + 3) & ~3;
   for (int e = tid; e < p * p; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     const int lo = min(i, j), hi = max(i, j);
     const int J = hi >> 4;
-    X[e] = a.E[e_off(q, J) + (int64_t)(q + lo) * 16 + (hi & 15)];
+    X[e] = a.E[e_off(q4, J) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
   }
   for (int e = tid; e < q * p; e += kSmallThreads) {
     const int i = e / p, j = e % p;
-    a.Bt[e] = a.E[e_off(q, j >> 4) + (int64_t)i * 16 + (j & 15)];
+    a.Bt[e] = a.E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
   }
   __syncthreads();
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
@@ -452,17 +536,17 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
   }
-  //    -B~_J = -[B~[:, J]; R~[0:16J, J]], rows padded to a multiple of 4.
+  //    -B~_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]].
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
-    const int rows = (q + b0 + 3) & ~3;
-    double* bn = a.bneg + 16 * ((int64_t)J * ((q + 3) & ~3) + 8 * (int64_t)J * (J - 1));
+    const int rows = q4 + b0;
+    double* bn = a.bneg + 16 * ((int64_t)J * q4 + 8 * (int64_t)J * (J - 1));
     for (int e = tid; e < rows * 16; e += kSmallThreads) {
       const int k = e >> 4, cc = e & 15;
       double val = 0.0;
       if (cc < pb) {
         if (k < q) val = -a.Bt[(int64_t)k * p + b0 + cc];
-        else if (k < q + b0) val = -M[(int64_t)(k - q) * p + b0 + cc];
+        else if (k >= q4) val = -M[(int64_t)(k - q4) * p + b0 + cc];
       }
       bn[e] = val;
     }

@@ -61,7 +61,8 @@ def growth_blocks(m: int, n0: int, p: int, nblocks: int, kappa_lo: float,
     U0 = orthonormal(g0, m, n0)
     V0 = orthonormal(g0, n0, n0)
     A0 = np.asfortranarray((U0 * singular_values(n0, 1e2)) @ V0.T)
-    Us = [U0]
+    Uall = np.empty((m, n0 + nblocks * p), order="F")
+    Uall[:, :n0] = U0
     blocks, kappas = [], []
     for k in range(1, nblocks + 1):
         g = rng(seed, k, m, p)
@@ -69,12 +70,12 @@ def growth_blocks(m: int, n0: int, p: int, nblocks: int, kappa_lo: float,
         kappa = 10.0 ** lk
         Uk = orthonormal(g, m, p)
         Vk = orthonormal(g, p, p)
-        prev = np.concatenate(Us, axis=1)
-        Gk = g.standard_normal((prev.shape[1], p))
-        W = (Uk * singular_values(p, kappa)) @ Vk.T + coupling * (prev @ Gk)
+        q = n0 + (k - 1) * p
+        Gk = g.standard_normal((q, p))
+        W = (Uk * singular_values(p, kappa)) @ Vk.T + coupling * (Uall[:, :q] @ Gk)
         blocks.append(np.asfortranarray(W))
         kappas.append(kappa)
-        Us.append(Uk)
+        Uall[:, q:q + p] = Uk
     return A0, blocks, kappas
 
 

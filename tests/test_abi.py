@@ -16,9 +16,12 @@ def sq():
 
 
 def test_header_symbols_exported(sq):
-    hdr = open(os.path.join(ROOT, "include", "sqr.h")).read()
-    names = set(re.findall(r"^\s*(?:int|void|int64_t)\s+(sqr_\w+)\s*\(", hdr, re.M))
-    assert {"sqr_orth", "sqr_append", "sqr_free"} <= names
+    import glob
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        names |= set(re.findall(r"^\s*(?:int|void|int64_t)\s+(sqr_\w+)\s*\(",
+                                open(h).read(), re.M))
+    assert {"sqr_orth", "sqr_append", "sqr_free", "sqr_prof_read"} <= names
     lib = ctypes.CDLL(sq.LIB_PATH)
     for nm in names:
         assert hasattr(lib, nm), nm
