@@ -46,6 +46,27 @@ def step_bytes(m, n0, p, infos):
     return total
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "block_pass_apply_growth_m1e6_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2507_07788_amd", "csrc", "sqr_kernels.hip")
+
+
+def measured_traffic(alg_bytes_per_launch):
+    """HBM bytes per apply launch of the streaming kernel, from the committed
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain-copy calibration), as
+    measured/algorithmic ratio times this run's algorithmic bytes per launch.
+    None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE)
+                  if ":" in line and not line.startswith("#"))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256", "").strip() != sha:
+            return None
+        return round(float(kv["measured_over_algorithmic"]) * alg_bytes_per_launch)
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +75,8 @@ def main():
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--blocks", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain device copy of 1 GiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -74,6 +97,14 @@ def main():
         t = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device="cuda").t()
         t.copy_(torch.from_numpy(np.ascontiguousarray(X)))
         return t
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        del src, dst
 
     A0d = to_dev(A0)
     Wd = [to_dev(W) for W in Ws]
@@ -118,10 +149,12 @@ def main():
 
     nl, ms, by = prof["apply"]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = measured_traffic(by / max(nl, 1))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "block_pass (apply)", "launches": nl,
-                "avg_launch_us": round(ms * 1e3 / max(nl, 1), 2)}
+                "avg_launch_us": round(ms * 1e3 / max(nl, 1), 2),
+                "algorithmic_bytes_per_launch": round(by / max(nl, 1))}
 
     cpu = None
     if not args.no_cpu_baseline:
