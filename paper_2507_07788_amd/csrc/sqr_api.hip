@@ -28,9 +28,9 @@ constexpr int kMaxSlots = 1024;
 // Leading dimensions up to this keep every per-lane buffer offset,
 // (3 ld + m) * 8 bytes, below 4 GiB.
 constexpr int64_t kMaxLd = (int64_t)1 << 27;
-constexpr int kStage1 = 16;                    // slots summed per first-stage group
+constexpr int kStage1 = 64;                    // slots summed per reduction group
 constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
-constexpr int kSmallLdsMax = 88;               // p up to this keeps X, M in LDS
+constexpr size_t kSmallLdsBytes = 136 * 1024;  // small_step arena in LDS up to this
 
 // ---- measurement records (sqr_prof.h) ----
 struct ProfRec { hipEvent_t e0, e1; int kind; double bytes; int64_t call; int phase; int real; };
@@ -97,36 +97,37 @@ struct sqr_basis {
   void* ws = nullptr;
   Ctrl* ctrl = nullptr;
   Ctrl* ctrl_host = nullptr;         // pinned
-  double *part = nullptr, *stage = nullptr, *E = nullptr;
-  double *X = nullptr, *M = nullptr, *Bt = nullptr, *Rnew = nullptr;
+  double *part = nullptr, *stage = nullptr;
+  double *X = nullptr;
   double *bneg = nullptr, *rinv = nullptr;
 };
 
 namespace {
 
 typedef void (*BlockKernel)(BlockPassArgs);
-struct Variant { int nt; BlockKernel gram, apply; };
+// nt = S tiles per wave, wpt = waves sharing a row tile (4 / wpt row tiles
+// in flight per workgroup); a variant covers nt * wpt tiles of S.
+struct Variant { int nt, wpt; BlockKernel gram, apply; };
+int g_occ[2][32];     // workgroups per CU of each variant (gram, apply)
+int g_ncu = 0;
+#define SQR_VARIANT(NT, W) {NT, W, block_pass<NT, W, false>, block_pass<NT, W, true>}
 const Variant kVariants[] = {
-  {1, block_pass<1, false>, block_pass<1, true>},
-  {2, block_pass<2, false>, block_pass<2, true>},
-  {3, block_pass<3, false>, block_pass<3, true>},
-  {4, block_pass<4, false>, block_pass<4, true>},
-  {5, block_pass<5, false>, block_pass<5, true>},
-  {6, block_pass<6, false>, block_pass<6, true>},
-  {7, block_pass<7, false>, block_pass<7, true>},
-  {8, block_pass<8, false>, block_pass<8, true>},
-  {9, block_pass<9, false>, block_pass<9, true>},
+  SQR_VARIANT(1, 1), SQR_VARIANT(1, 2), SQR_VARIANT(2, 2),
+  SQR_VARIANT(2, 4), SQR_VARIANT(3, 4), SQR_VARIANT(4, 4), SQR_VARIANT(5, 4),
+  SQR_VARIANT(6, 4), SQR_VARIANT(7, 4), SQR_VARIANT(8, 4), SQR_VARIANT(9, 4),
 };
+#undef SQR_VARIANT
 
-// Variant by S tiles per wave (the four waves of a workgroup share them).
+// Smallest variant whose S capacity covers ns tiles (listed by capacity).
 const Variant* pick_variant(int ns) {
-  const int ntw = std::max(1, (ns + kWaveTiles - 1) / kWaveTiles);
   for (const Variant& v : kVariants)
-    if (v.nt >= ntw) return &v;
+    if (v.nt * v.wpt >= std::max(ns, 1)) return &v;
   return nullptr;
 }
 
 size_t block_lds_bytes() {
+  // main loop: partial T tiles + transposition tiles; the final cross-group
+  // reduction (at most 4 groups x 2 tiles, or 2 groups x 5 tiles) fits in it
   return 8 * ((size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch);
 }
 
@@ -138,7 +139,24 @@ void set_kernel_attributes() {
     (void)hipFuncSetAttribute((const void*)v.apply, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
   }
   (void)hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      2 * kSmallLdsMax * kSmallLdsMax * 8);
+                            (int)kSmallLdsBytes);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      g_ncu < 1)
+    g_ncu = 256;
+  int i = 0;
+  for (const Variant& v : kVariants) {
+    for (int ap = 0; ap < 2; ++ap) {
+      int n = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)(ap ? v.apply : v.gram),
+                                                        kThreads, block_lds_bytes()) != hipSuccess ||
+          n < 1)
+        n = 1;
+      g_occ[ap][i] = n;
+    }
+    ++i;
+  }
   g_attr_done = true;
 }
 
@@ -163,15 +181,13 @@ int alloc_workspace(sqr_basis* b) {
   b->slots = (int)std::max<int64_t>(1, slots);
   const int64_t ng1 = (b->slots + kStage1 - 1) / kStage1;
   const int64_t sq = cap * cap;
+  int64_t arena = 0;
+  for (int64_t p = 1; p <= cap; ++p) arena = std::max<int64_t>(arena, small_arena((int)(cap - p), (int)p));
   size_t doubles = 0;
   auto take = [&](int64_t n) { size_t off = doubles; doubles += (size_t)round4(n) + 32; return off; };
   const size_t o_part = take((int64_t)b->slots * tl);
   const size_t o_stage = take(ng1 * tl);
-  const size_t o_E = take(tl);
-  const size_t o_X = take(sq);
-  const size_t o_M = take(sq);
-  const size_t o_Bt = take(sq);
-  const size_t o_Rnew = take(sq);
+  const size_t o_X = take(arena);
   const size_t o_bneg = take(worst_bneg_len(cap));
   const size_t o_rinv = take(nblocks(cap) * 256);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
@@ -188,8 +204,8 @@ int alloc_workspace(sqr_basis* b) {
     b->ws_bytes = doubles * 8;
   }
   double* base = (double*)b->ws;
-  b->part = base + o_part; b->stage = base + o_stage; b->E = base + o_E;
-  b->X = base + o_X; b->M = base + o_M; b->Bt = base + o_Bt; b->Rnew = base + o_Rnew;
+  b->part = base + o_part; b->stage = base + o_stage;
+  b->X = base + o_X;
   b->bneg = base + o_bneg; b->rinv = base + o_rinv;
   b->ctrl = (Ctrl*)(base + o_ctrl);
   if (!b->ctrl_host &&
@@ -207,12 +223,26 @@ struct Call {
   double* y; int64_t ldy;          // output block
 };
 
+int variant_index(const Variant* v) { return (int)(v - kVariants); }
+
 int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   const int64_t P = nblocks(c.p);
   const int64_t tl = total_len(c.q, c.p);
   const int64_t tiles = (b->m + 15) / 16;
-  const int nwg = (int)std::min<int64_t>(b->slots, (tiles + kWaves - 1) / kWaves);
   const bool apply = phase > 0;
+  // One grid size for every block of the pass (the slots are reduced
+  // together): resident workgroups of the most demanding block's variant,
+  // capped by the slot capacity and by the row tiles available.
+  int64_t nwg = b->slots;
+  for (int64_t J = 0; J < P; ++J) {
+    const int ks = (int)round4(c.q) + (int)(16 * J);
+    const Variant* v = pick_variant((ks + 15) / 16);
+    if (!v) return SQR_EDIM;
+    const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
+    nwg = std::min<int64_t>(nwg, (tiles + (kWaves / v->wpt) - 1) / (kWaves / v->wpt));
+  }
+  nwg = std::max<int64_t>(nwg, 1);
   for (int64_t J = 0; J < P; ++J) {
     BlockPassArgs a;
     memset(&a, 0, sizeof(a));
@@ -232,7 +262,6 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     a.copy_if_done = (phase == 1);
     const int ks = (int)round4(a.n1) + a.n2;   // columns of S with the padding
     const Variant* v = pick_variant((ks + 15) / 16);
-    if (!v) return SQR_EDIM;
     void* args[] = {&a};
     ProfRec rec{};
     if (g_prof_on) {
@@ -242,36 +271,34 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       rec.call = b->call_id; rec.phase = phase; rec.real = -1;
       if (rec.e0) (void)hipEventRecord(rec.e0, s);
     }
-    if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3(nwg), dim3(kThreads),
-                        args, block_lds_bytes(), s) != hipSuccess)
+    if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
+                        dim3(kThreads), args, block_lds_bytes(), s) != hipSuccess)
       return SQR_EHIP;
     if (g_prof_on && rec.e0 && rec.e1) {
       (void)hipEventRecord(rec.e1, s);
       g_prof.push_back(rec);
     }
   }
-  // fixed-order two-stage reduction of the nwg slots
-  const int ng1 = (nwg + kStage1 - 1) / kStage1;
-  const dim3 rb((unsigned)((tl + 255) / 256));
-  hipLaunchKernelGGL(reduce_slots, dim3(rb.x, ng1), dim3(256), 0, s,
-                     (const double*)b->part, nwg, tl, tl, kStage1, b->stage,
-                     (const int*)&b->ctrl->done);
-  hipLaunchKernelGGL(reduce_slots, dim3(rb.x, 1), dim3(256), 0, s,
-                     (const double*)b->stage, ng1, tl, tl, ng1, b->E,
+  // Fixed-order reduction of the nwg slots in groups of kStage1; small_step
+  // adds the group sums in group order.
+  const int ng1 = (int)((nwg + kStage1 - 1) / kStage1);
+  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 255) / 256), ng1), dim3(256), 0, s,
+                     (const double*)b->part, (int)nwg, tl, tl, kStage1, b->stage,
                      (const int*)&b->ctrl->done);
   SmallArgs k;
   memset(&k, 0, sizeof(k));
-  k.E = b->E; k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+  k.E = b->stage; k.ngroups = ng1; k.estride = tl;
+  k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
   k.m = b->m; k.phase = phase;
   k.R = b->R; k.ldr = b->ldr;
-  k.X = b->X; k.M = b->M; k.Bt = b->Bt; k.Rnew = b->Rnew;
+  k.X = b->X;
   k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
   k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
   k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
   k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
-  k.lds_matrices = c.p <= kSmallLdsMax;
-  const size_t slds = k.lds_matrices ? 2 * 8 * c.p * c.p : 0;
-  hipLaunchKernelGGL(small_step, dim3(1), dim3(1024), slds, s, k);
+  const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
+  k.lds_matrices = arena <= kSmallLdsBytes;
+  hipLaunchKernelGGL(small_step, dim3(1), dim3(kSmallThreads), k.lds_matrices ? arena : 0, s, k);
   return hipGetLastError() == hipSuccess ? SQR_OK : SQR_EHIP;
 }
 

@@ -42,7 +42,10 @@ struct BlockPassArgs {
 
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
-  const double* E;       // reduced partial Gramians of the pass, block after block
+  const double* E;       // partially reduced Gramians of the pass: ngroups copies,
+                         // estride apart, each holding the blocks one after another
+  int32_t ngroups;
+  int64_t estride;
   int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2)
   int32_t q;             // basis width (append), 0 for orth
   int32_t p;             // block width being orthogonalised
@@ -52,19 +55,16 @@ struct SmallArgs {
   // caller R (column-major, ldr): orth uses R[0:p,0:p]; append writes
   // B = R[0:q, q:q+p] and the new diagonal block R[q:q+p, q:q+p]
   double* R; int64_t ldr;
-  // workspace
-  double* X;             // p x p (row-major), the Gramian / Schur complement
-  double* M;             // p x p (row-major), factorised in place
-  double* Rt;            // p x p (row-major), R~ of this pass
-  double* Bt;            // q x p (row-major), B~ of this pass
-  double* Rnew;          // scratch p x p / q x p
+  // workspace arena for the small matrices when they do not fit in LDS:
+  // X, M, old R block (p x p each), B~ (q x p), scratch (row-major)
+  double* X;
   double* bneg;          // per block J: (q + 16J rounded up to 4) x 16, row-major
   double* rinv;          // per block J: 16 x 16
   Ctrl* ctrl;
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
   double tol, u;
-  int32_t lds_matrices;  // 1: X, M live in LDS instead of the workspace
+  int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X
 };
 
 }  // namespace sqr

@@ -63,23 +63,28 @@ constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
 // rounded up to 4 | s2 (n2 columns, a multiple of 16)], so every k-slice of
 // four columns lies in a single segment.  ks = q4 + n2 columns in all.
 //
-// Work split: a workgroup of four waves processes one 16-row tile at a time.
-// The 16-column tiles of S are dealt out round-robin (tile I -> wave I % 4),
-// so each wave keeps only its share of S, of -B~ and of the Gram
-// accumulators in registers.  The waves' partial sums of S B~ meet in LDS
-// (fixed order), every wave forms the same Y tile, and each wave then adds
-// S_I^T Y for its own tiles I.  Wave 0 owns the block input, the Y store and
-// Y^T Y.
-constexpr int kWaveTiles = 4;  // waves sharing the S tiles of a row tile
-constexpr int kTPart = 256;    // doubles per partial 16x16 tile in LDS
+// Work split: the four waves of a workgroup form 4/WPT groups of WPT waves;
+// each group processes its own 16-row tile per step, so a workgroup keeps
+// 4/WPT tiles in flight.  Within a group the 16-column tiles of S are dealt
+// out round-robin (tile I -> member I % WPT), so each wave keeps only its
+// share of S, of -B~ and of the Gram accumulators in registers.  With
+// WPT > 1 the members' partial sums of S B~ meet in LDS (fixed order) and
+// every member forms the same Y tile.  Member 0 of a group owns the block
+// input, the Y store and Y^T Y.  Groups' Gram partials are summed in group
+// order at the end.
+constexpr int kTPart = 256;    // doubles per 16x16 tile in LDS
 
-template <int NTW, bool APPLY>
+template <int NTW, int WPT, bool APPLY>
 __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   // LDS: double-buffered partial T tiles (2 x 4 x 256 doubles), then one
-  // 16x17 transposition tile per wave.
+  // 16x17 transposition tile per wave; the final cross-group reduction
+  // reuses the area.
   extern __shared__ double lds[];
+  constexpr int G = kWaves / WPT;      // row tiles in flight per workgroup
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int grp = wave / WPT;          // row-tile group
+  const int mem = wave % WPT;          // member within the group
   const int x = lane & 15;
   const int g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
@@ -121,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     for (int j = 0; j < NTW; ++j)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int s = 4 * (wave + kWaveTiles * j) + jj;
+        const int s = 4 * (mem + WPT * j) + jj;
         bn[j][jj] = (s < nk) ? a.bneg[(4 * s + g) * 16 + x] : 0.0;
       }
 #pragma unroll
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
       for (int j = 0; j < NTW; ++j)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int s = 4 * (wave + kWaveTiles * j) + jj;
+          const int s = 4 * (mem + WPT * j) + jj;
           const bool first = (4 * s < q4) || a.n2 == 0;
           const int cs = first ? 4 * s : 4 * s - q4;
           const int hi = first ? hi1 : hi2;
@@ -179,24 +184,30 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     }
   };
 
+  // Step k handles row tile t0 + k*G + grp of this workgroup; every wave runs
+  // the same number of steps (barriers), a group past the range works on a
+  // clamped tile with its Y forced to zero and no stores.
   double snext[NTW][4];
   d4 wnext;
-  if (t0 < t1) load_tile(t0, snext, wnext);
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t row = t * 16 + x;
-    const bool row_ok = row < a.m;
+  load_tile(min(t0 + grp, t1 - 1), snext, wnext);
+  int it = 0;
+  for (int64_t t = t0; t < t1; t += G, ++it) {
+    const int64_t tile = t + grp;
+    const bool tile_ok = tile < t1;
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = tile_ok && row < a.m;
     double sreg[NTW][4];
 #pragma unroll
     for (int j = 0; j < NTW; ++j)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) sreg[j][jj] = snext[j][jj];
     const d4 w = wnext;
-    // prefetch the next row tile (clamped to a valid tile)
-    load_tile(min(t + 1, t1 - 1), snext, wnext);
+    // prefetch this group's next row tile (clamped to a valid tile)
+    load_tile(min(tile + G, t1 - 1), snext, wnext);
     d4 y;
     if (APPLY) {
-      // Partial T^T over my slices (two chains), wave 0 starts from W^T.
-      d4 c0 = (wave == 0) ? w : d4{0.0, 0.0, 0.0, 0.0};
+      // Partial T^T over my slices (two chains); member 0 starts from W^T.
+      d4 c0 = (mem == 0) ? w : d4{0.0, 0.0, 0.0, 0.0};
       d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int j = 0; j < NTW; ++j)
@@ -205,24 +216,26 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
           if (jj & 1) c1 = mfma(bn[j][jj], sreg[j][jj], c1);
           else        c0 = mfma(bn[j][jj], sreg[j][jj], c0);
         }
-      const d4 cp = c0 + c1;
-      double* tp = tpart + ((t & 1) * kWaves + wave) * kTPart;
+      d4 tt = c0 + c1;
+      if (WPT > 1) {
+        double* tp = tpart + ((it & 1) * kWaves + wave) * kTPart;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = cp[r];
-      __syncthreads();
-      // T^T = sum of the partials in wave order.
-      d4 tt = d4{0.0, 0.0, 0.0, 0.0};
-      const double* tb = tpart + (t & 1) * kWaves * kTPart;
+        for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = tt[r];
+        __syncthreads();
+        // T^T = sum of the group's partials in member order.
+        tt = d4{0.0, 0.0, 0.0, 0.0};
+        const double* tb = tpart + ((it & 1) * kWaves + grp * WPT) * kTPart;
 #pragma unroll
-      for (int v = 0; v < kWaves; ++v)
+        for (int v = 0; v < WPT; ++v)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tt[r] += tb[v * kTPart + r * 64 + lane];
+          for (int r = 0; r < 4; ++r) tt[r] += tb[v * kTPart + r * 64 + lane];
+      }
       // Y^T = D^T T^T: register r of T^T is the B operand of k-slice r.
       y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) y = mfma(rinv[r], tt[r], y);
       if (!row_ok) y = d4{0.0, 0.0, 0.0, 0.0};
-      if (wave == 0) {
+      if (mem == 0 && tile_ok) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = g + 4 * r;
@@ -231,6 +244,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
       }
     } else {
       y = w;
+      if (!tile_ok) y = d4{0.0, 0.0, 0.0, 0.0};
     }
     // Y through wave-private LDS: the row index becomes the contraction index
     // (k-slot g of slice u <-> row g + 4u).
@@ -241,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) yb[u] = tr[(g + 4 * u) * kYPitch + x];
     wave_lds_sync();
-    if (wave == 0) {
+    if (mem == 0) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) accg = mfma(yb[u], yb[u], accg);
     }
@@ -263,18 +277,47 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   // Slot layout: rows 0..ks-1 hold S^T Y, rows ks..ks+15 hold Y^T Y, 16
   // doubles per row.  Tile I row (g + 4r) is S column 16I + g + 4r.
   double* out = a.part + (int64_t)blockIdx.x * a.part_stride + a.part_off;
+  if (G == 1) {
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) {
-    const int I = wave + kWaveTiles * j;
+    for (int j = 0; j < NTW; ++j) {
+      const int I = mem + WPT * j;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = 16 * I + g + 4 * r;
-      if (I < ns && rr < ks) out[rr * 16 + x] = acc[j][r];
+      for (int r = 0; r < 4; ++r) {
+        const int rr = 16 * I + g + 4 * r;
+        if (I < ns && rr < ks) out[rr * 16 + x] = acc[j][r];
+      }
     }
-  }
-  if (wave == 0) {
+    if (mem == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[(ks + g + 4 * r) * 16 + x] = accg[r];
+      for (int r = 0; r < 4; ++r) out[(ks + g + 4 * r) * 16 + x] = accg[r];
+    }
+  } else {
+    // Groups hold partials of the same tiles: sum them in group order.
+    // red[grp][slot]: slot mem + WPT*j for S tiles, WPT*NTW for Y^T Y.
+    constexpr int kSlots = WPT * NTW + 1;
+    __syncthreads();
+    double* red = lds;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[(grp * kSlots + mem + WPT * j) * kTPart + (g + 4 * r) * 16 + x] = acc[j][r];
+    if (mem == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[(grp * kSlots + WPT * NTW) * kTPart + (g + 4 * r) * 16 + x] = accg[r];
+    }
+    __syncthreads();
+    const int rows = ks + 16;
+    for (int e = threadIdx.x; e < rows * 16; e += kThreads) {
+      const int rr = e >> 4, c = e & 15;
+      const int slot = (rr < ks) ? (rr >> 4) : WPT * NTW;
+      const int within = (rr < ks) ? (rr & 15) : (rr - ks);
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < G; ++v) s += red[(v * kSlots + slot) * kTPart + within * 16 + c];
+      out[e] = s;
+    }
   }
 }
 
@@ -291,6 +334,7 @@ __global__ __launch_bounds__(256) void reduce_slots(const double* __restrict__ i
   const int s0 = blockIdx.y * G;
   const int s1 = min(nslots, s0 + G);
   double s = 0.0;
+#pragma unroll 8
   for (int i = s0; i < s1; ++i) s += in[(int64_t)i * stride + e];
   out[(int64_t)blockIdx.y * stride + e] = s;
 }
@@ -299,25 +343,27 @@ __global__ __launch_bounds__(256) void reduce_slots(const double* __restrict__ i
 // ---------------------------------------------------------------------------
 // small_step: one workgroup of 1024 threads finishes a pass.
 // ---------------------------------------------------------------------------
-constexpr int kSmallThreads = 1024;
+constexpr int kSmallThreads = 256;
+constexpr int kSmallWaves = kSmallThreads / 64;
 
-// Deterministic workgroup sum (fixed tree over thread ids).
+// Deterministic workgroup sum: a fixed butterfly inside each wave, then the
+// wave sums in wave order.  Every thread gets the result.
 __device__ double block_sum(double v, double* buf) {
-  const int tid = threadIdx.x;
-  buf[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wv = threadIdx.x >> 6;
   __syncthreads();
-  for (int s = kSmallThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) buf[tid] += buf[tid + s];
-    __syncthreads();
-  }
-  const double r = buf[0];
+  if ((threadIdx.x & 63) == 0) buf[wv] = v;
   __syncthreads();
-  return r;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kSmallWaves; ++i) s += buf[i];
+  return s;
 }
 
-// Offset (in doubles) of block J's partial Gramian inside E: block J' holds
-// (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4 (rows q..q4-1
-// belong to the zero padding of S and are ignored).
+// Offset (in doubles) of block J's partial Gramian inside a reduced slot:
+// block J' holds (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4
+// (rows q..q4-1 belong to the zero padding of S and are ignored).
 __device__ __forceinline__ int64_t e_off(int q4, int J) {
   return 16 * ((int64_t)J * (q4 + 16) + 8 * (int64_t)J * (J - 1));
 }
@@ -345,18 +391,31 @@ __device__ bool chol_upper(double* M, int p) {
   return true;
 }
 
+// Doubles small_step keeps in LDS when they fit: X, M, R_old (p x p each),
+// B~ (q x p) and a scratch of max(q p, p p).
+__host__ __device__ inline int64_t small_arena(int q, int p) {
+  const int64_t pp = (int64_t)p * p, qp = (int64_t)q * p;
+  return 3 * pp + qp + (qp > pp ? qp : pp);
+}
+
 __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[kSmallThreads];
+  __shared__ double red[kSmallWaves];
   __shared__ double v[kMaxCols], w[kMaxCols];
   Ctrl* c = a.ctrl;
   if (c->done) return;
   const int tid = threadIdx.x;
   const int p = a.p, q = a.q;
-  double* X = a.lds_matrices ? lds : a.X;
-  double* M = a.lds_matrices ? lds + (int64_t)p * p : a.M;
+  const int64_t pp = (int64_t)p * p, qp = (int64_t)q * p;
+  double* base = a.lds_matrices ? lds : a.X;   // arena (LDS, or workspace)
+  double* X = base;
+  double* M = X + pp;
+  double* Ro = M + pp;          // old diagonal block of R (row-major)
+  double* Bt = Ro + pp;         // B~ (row-major q x p)
+  double* Rn = Bt + qp;         // scratch
   double* R = a.R;
   const int64_t ldr = a.ldr;
+  const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
 
   if (a.phase == 0) {
     // Algorithm 1: R = I.  Algorithm 2: B = 0, R = I_p, and the block below
@@ -371,32 +430,43 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     }
   }
 
-  // 1. Gramian blocks: B~ = E[0:q, :], G = E[q:q+p, :] (upper, mirrored).
+  // 1. Gramian blocks from the reduced slots (the last reduction stage, in
+  //    group order): B~ = E[0:q, :], G = E[q:q+p, :] (upper, mirrored).
   const int q4 = (q + 3) & ~3;
   for (int e = tid; e < p * p; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     const int lo = min(i, j), hi = max(i, j);
-    const int J = hi >> 4;
-    X[e] = a.E[e_off(q4, J) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
+    const int64_t idx = e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15);
+    double s = 0.0;
+    for (int gi = 0; gi < a.ngroups; ++gi) s += a.E[(int64_t)gi * a.estride + idx];
+    X[e] = s;
   }
-  for (int e = tid; e < q * p; e += kSmallThreads) {
+  for (int e = tid; e < qp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
-    a.Bt[e] = a.E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
+    const int64_t idx = e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15);
+    double s = 0.0;
+    for (int gi = 0; gi < a.ngroups; ++gi) s += a.E[(int64_t)gi * a.estride + idx];
+    Bt[e] = s;
+  }
+  // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2)
+  for (int e = tid; e < pp; e += kSmallThreads) {
+    const int i = e / p, j = e % p;
+    Ro[e] = (a.phase == 0) ? (i == j ? 1.0 : 0.0) : R[roff + i + (int64_t)j * ldr];
   }
   __syncthreads();
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
   if (a.mode == 1 && q > 0) {
-    for (int e = tid; e < p * p; e += kSmallThreads) {
+    for (int e = tid; e < pp; e += kSmallThreads) {
       const int i = e / p, j = e % p;
       double s = 0.0;
-      for (int k = 0; k < q; ++k) s += a.Bt[(int64_t)k * p + i] * a.Bt[(int64_t)k * p + j];
+      for (int k = 0; k < q; ++k) s += Bt[(int64_t)k * p + i] * Bt[(int64_t)k * p + j];
       X[e] -= s;
     }
     __syncthreads();
   }
   // 3. ||X - I||_F.
   double part = 0.0;
-  for (int e = tid; e < p * p; e += kSmallThreads) {
+  for (int e = tid; e < pp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     const double d = X[e] - (i == j ? 1.0 : 0.0);
     part += d * d;
@@ -427,7 +497,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   double sigma = 0.0;
   bool ok = false;
   if (!shifted) {
-    for (int e = tid; e < p * p; e += kSmallThreads) M[e] = X[e];
+    for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
     ++attempts;
     ok = chol_upper(M, p);
     shifted = !ok;
@@ -439,14 +509,14 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     double lam = 0.0;
     bool early = false;
     for (int s = 0; s < a.power_steps; ++s) {
-      double pp = 0.0;
+      double pp2 = 0.0;
       for (int i = tid; i < p; i += kSmallThreads) {
         double t = 0.0;
         for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
         w[i] = t;
-        pp += t * t;
+        pp2 += t * t;
       }
-      const double nrm = sqrt(block_sum(pp, red));
+      const double nrm = sqrt(block_sum(pp2, red));
       if (!(nrm > 0.0) || !isfinite(nrm)) {
         lam = isfinite(nrm) ? nrm : __builtin_nan("");
         early = true;
@@ -456,20 +526,20 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       __syncthreads();
     }
     if (!early) {
-      double pp = 0.0;
+      double pp2 = 0.0;
       for (int i = tid; i < p; i += kSmallThreads) {
         double t = 0.0;
         for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
-        pp += v[i] * t;
+        pp2 += v[i] * t;
       }
-      lam = fabs(block_sum(pp, red));
+      lam = fabs(block_sum(pp2, red));
     }
     const double mm = (double)a.m;
     const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
                                      : (mm * q + (double)q * (q + 1));
     sigma = fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
     for (int esc = 0;; ++esc) {
-      for (int e = tid; e < p * p; e += kSmallThreads)
+      for (int e = tid; e < pp; e += kSmallThreads)
         M[e] = X[e] + ((e / p == e % p) ? sigma : 0.0);
       ++attempts;
       ok = chol_upper(M, p);
@@ -488,32 +558,20 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     }
   }
   __syncthreads();
-  // 6. B <- B + B~ R (old R), then R <- R~ R (Algorithm 2; Algorithm 1).
-  const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
+  // 6. B <- B + B~ R_old, then R <- R~ R_old (Algorithm 2; Algorithm 1).
   if (a.mode == 1 && q > 0) {
-    for (int e = tid; e < q * p; e += kSmallThreads) {
+    for (int e = tid; e < qp; e += kSmallThreads) {
       const int i = e / p, j = e % p;
       double s = 0.0;
-      for (int k = 0; k <= j; ++k) s += a.Bt[(int64_t)i * p + k] * R[roff + k + (int64_t)j * ldr];
-      a.Rnew[e] = s;
+      for (int k = 0; k <= j; ++k) s += Bt[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+      R[i + (int64_t)(q + j) * ldr] += s;
     }
-    __syncthreads();
-    for (int e = tid; e < q * p; e += kSmallThreads) {
-      const int i = e / p, j = e % p;
-      R[i + (int64_t)(q + j) * ldr] += a.Rnew[e];
-    }
-    __syncthreads();
   }
-  for (int e = tid; e < p * p; e += kSmallThreads) {
+  for (int e = tid; e < pp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     double s = 0.0;
-    for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * R[roff + k + (int64_t)j * ldr];
-    a.Rnew[e] = (i <= j) ? s : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < p * p; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
-    R[roff + i + (int64_t)j * ldr] = a.Rnew[e];
+    for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+    R[roff + i + (int64_t)j * ldr] = (i <= j) ? s : 0.0;
   }
   // 7. Operands of the next pass.  D_J = inverse of the diagonal block J of
   //    R~ (identity beyond p), by back substitution on each column.
@@ -545,7 +603,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       const int k = e >> 4, cc = e & 15;
       double val = 0.0;
       if (cc < pb) {
-        if (k < q) val = -a.Bt[(int64_t)k * p + b0 + cc];
+        if (k < q) val = -Bt[(int64_t)k * p + b0 + cc];
         else if (k >= q4) val = -M[(int64_t)(k - q4) * p + b0 + cc];
       }
       bn[e] = val;
