@@ -4,11 +4,12 @@
 // The tall operands stay in HBM, column-major.  A pass over them is split
 // into 16-column blocks.  For block J one launch of `block_pass` streams
 // 16-row tiles and, per tile,
-//   (1) forms T_J = W_J - S B~_J, the Q <- Q - Q_in B~ step of Algorithm 2
-//       and the off-diagonal part of the blocked triangular solve,
-//   (2) forms Y_J = T_J D_J with D_J the inverse of the 16x16 diagonal block
-//       of R~ (so all blocks together give Y = T R~^{-1}),
-//   (3) writes Y_J and accumulates the partial Gramian [S Y_J]^T Y_J of the
+//   (1) forms Y_J = W_J D_J + S C_J, where D_J is the inverse of the 16x16
+//       diagonal block of R~ and C_J = -[B~_J; R~_<J,J] D_J: the
+//       Q <- (Q - Q_in B~) R~^{-1} step of Algorithm 2 (Q <- Q R~^{-1} of
+//       Algorithm 1) as a blocked triangular solve whose diagonal blocks are
+//       multiplied by their inverses,
+//   (2) writes Y_J and accumulates the partial Gramian [S Y_J]^T Y_J of the
 //       next pass (Algorithm 1's X <- Q^T Q; Algorithm 2's B~ <- Q_in^T Q and
 //       Q^T Q), so every pass reads the tall data once.
 // S is the concatenation of the existing basis Q_in and the blocks < J of the
@@ -206,34 +207,41 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     load_tile(min(tile + G, t1 - 1), snext, wnext);
     d4 y;
     if (APPLY) {
-      // Partial T^T over my slices (two chains); member 0 starts from W^T.
-      d4 c0 = (mem == 0) ? w : d4{0.0, 0.0, 0.0, 0.0};
+      // Partial Y^T over my slices (two chains): Y_J = W_J D_J + S C_J with
+      // C_J = -B~_J D_J.  Member 0 adds D^T W^T: register r of W^T (D layout)
+      // is the B operand of k-slice r.
+      d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
       d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
+      if (mem == 0) {
+        c0 = mfma(rinv[0], w[0], c0);
+        c1 = mfma(rinv[1], w[1], c1);
+        c0 = mfma(rinv[2], w[2], c0);
+        c1 = mfma(rinv[3], w[3], c1);
+      }
 #pragma unroll
-      for (int j = 0; j < NTW; ++j)
+      for (int j = 0; j < NTW; ++j) {
+        if (mem + WPT * j < ns) {   // tile slots past the end of S hold zeros
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          if (jj & 1) c1 = mfma(bn[j][jj], sreg[j][jj], c1);
-          else        c0 = mfma(bn[j][jj], sreg[j][jj], c0);
+          for (int jj = 0; jj < 4; ++jj) {
+            if (jj & 1) c1 = mfma(bn[j][jj], sreg[j][jj], c1);
+            else        c0 = mfma(bn[j][jj], sreg[j][jj], c0);
+          }
         }
-      d4 tt = c0 + c1;
+      }
+      y = c0 + c1;
       if (WPT > 1) {
         double* tp = tpart + ((it & 1) * kWaves + wave) * kTPart;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = tt[r];
+        for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = y[r];
         __syncthreads();
-        // T^T = sum of the group's partials in member order.
-        tt = d4{0.0, 0.0, 0.0, 0.0};
+        // Y^T = sum of the group's partials in member order.
+        y = d4{0.0, 0.0, 0.0, 0.0};
         const double* tb = tpart + ((it & 1) * kWaves + grp * WPT) * kTPart;
 #pragma unroll
         for (int v = 0; v < WPT; ++v)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) tt[r] += tb[v * kTPart + r * 64 + lane];
+          for (int r = 0; r < 4; ++r) y[r] += tb[v * kTPart + r * 64 + lane];
       }
-      // Y^T = D^T T^T: register r of T^T is the B operand of k-slice r.
-      y = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) y = mfma(rinv[r], tt[r], y);
       if (!row_ok) y = d4{0.0, 0.0, 0.0, 0.0};
       if (mem == 0 && tile_ok) {
 #pragma unroll
@@ -262,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     // My S tiles through the same LDS tile: sreg[j][jj] = S[row x][16I + 4jj + g].
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
+      if (mem + WPT * j >= ns) continue;   // no such tile of S
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) tr[x * kYPitch + 4 * jj + g] = sreg[j][jj];
       wave_lds_sync();
@@ -594,17 +603,23 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
   }
-  //    -B~_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]].
+  __syncthreads();  // D_J complete (global, this workgroup)
+  //    C_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]] D_J, so the
+  //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
     const int rows = q4 + b0;
+    const double* D = a.rinv + J * 256;
     double* bn = a.bneg + 16 * ((int64_t)J * q4 + 8 * (int64_t)J * (J - 1));
     for (int e = tid; e < rows * 16; e += kSmallThreads) {
-      const int k = e >> 4, cc = e & 15;
+      const int kk = e >> 4, cc = e & 15;
       double val = 0.0;
-      if (cc < pb) {
-        if (k < q) val = -Bt[(int64_t)k * p + b0 + cc];
-        else if (k >= q4) val = -M[(int64_t)(k - q4) * p + b0 + cc];
+      if (cc < pb && (kk < q || kk >= q4)) {
+        for (int t = 0; t <= cc; ++t) {
+          const double src = (kk < q) ? Bt[(int64_t)kk * p + b0 + t]
+                                      : M[(int64_t)(kk - q4) * p + b0 + t];
+          val -= src * D[t * 16 + cc];
+        }
       }
       bn[e] = val;
     }
