@@ -28,7 +28,6 @@ constexpr int kMaxSlots = 1024;
 // Leading dimensions up to this keep every per-lane buffer offset,
 // (3 ld + m) * 8 bytes, below 4 GiB.
 constexpr int64_t kMaxLd = (int64_t)1 << 27;
-constexpr int kStage1 = 64;                    // slots summed per reduction group
 constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
 constexpr size_t kSmallLdsBytes = 136 * 1024;  // small_step arena in LDS up to this
 
@@ -179,14 +178,13 @@ int alloc_workspace(sqr_basis* b) {
   int64_t slots = std::min<int64_t>(kMaxSlots, (tiles + kWaves - 1) / kWaves);
   slots = std::min<int64_t>(slots, std::max<int64_t>(16, kPartBudget / (8 * tl)));
   b->slots = (int)std::max<int64_t>(1, slots);
-  const int64_t ng1 = (b->slots + kStage1 - 1) / kStage1;
   const int64_t sq = cap * cap;
   int64_t arena = 0;
   for (int64_t p = 1; p <= cap; ++p) arena = std::max<int64_t>(arena, small_arena((int)(cap - p), (int)p));
   size_t doubles = 0;
   auto take = [&](int64_t n) { size_t off = doubles; doubles += (size_t)round4(n) + 32; return off; };
   const size_t o_part = take((int64_t)b->slots * tl);
-  const size_t o_stage = take(ng1 * tl);
+  const size_t o_stage = take(tl);        // reduced Gramian blocks of a pass
   const size_t o_X = take(arena);
   const size_t o_bneg = take(worst_bneg_len(cap));
   const size_t o_rinv = take(nblocks(cap) * 256);
@@ -279,15 +277,13 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       g_prof.push_back(rec);
     }
   }
-  // Fixed-order reduction of the nwg slots in groups of kStage1; small_step
-  // adds the group sums in group order.
-  const int ng1 = (int)((nwg + kStage1 - 1) / kStage1);
-  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 255) / 256), ng1), dim3(256), 0, s,
-                     (const double*)b->part, (int)nwg, tl, tl, kStage1, b->stage,
+  // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
+  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 63) / 64)), dim3(64 * kRedWaves), 0, s,
+                     (const double*)b->part, (int)nwg, tl, tl, b->stage,
                      (const int*)&b->ctrl->done);
   SmallArgs k;
   memset(&k, 0, sizeof(k));
-  k.E = b->stage; k.ngroups = ng1; k.estride = tl;
+  k.E = b->stage;
   k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
   k.m = b->m; k.phase = phase;
   k.R = b->R; k.ldr = b->ldr;

@@ -42,10 +42,7 @@ struct BlockPassArgs {
 
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
-  const double* E;       // partially reduced Gramians of the pass: ngroups copies,
-                         // estride apart, each holding the blocks one after another
-  int32_t ngroups;
-  int64_t estride;
+  const double* E;       // reduced partial Gramians of the pass, block after block
   int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2)
   int32_t q;             // basis width (append), 0 for orth
   int32_t p;             // block width being orthogonalised

@@ -330,24 +330,34 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   }
 }
 
-// Sum slots [g*G, min(nslots, (g+1)*G)) of a partial buffer, element-wise, in
-// slot order.  Grid: (ceil(len/256), ceil(nslots/G)).
-__global__ __launch_bounds__(256) void reduce_slots(const double* __restrict__ in,
-                                                    int nslots, int64_t stride,
-                                                    int64_t len, int G,
-                                                    double* __restrict__ out,
-                                                    const int* done) {
+// Sum the nslots partial slots element-wise: a workgroup covers 64 elements
+// (one per lane, coalesced); its 16 waves take interleaved slots, each in
+// slot order, and the 16 wave sums are added in wave order.  The order of
+// every addition is fixed by nslots alone.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __restrict__ in,
+                                                             int nslots, int64_t stride,
+                                                             int64_t len,
+                                                             double* __restrict__ out,
+                                                             const int* done) {
+  __shared__ double part[kRedWaves][64];
   if (*done) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= len) return;
-  const int s0 = blockIdx.y * G;
-  const int s1 = min(nslots, s0 + G);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
+  if (e < len) {
 #pragma unroll 8
-  for (int i = s0; i < s1; ++i) s += in[(int64_t)i * stride + e];
-  out[(int64_t)blockIdx.y * stride + e] = s;
+    for (int i = wv; i < nslots; i += kRedWaves) s += in[(int64_t)i * stride + e];
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && e < len) {
+    double t = 0.0;
+#pragma unroll
+    for (int v = 0; v < kRedWaves; ++v) t += part[v][lane];
+    out[e] = t;
+  }
 }
-
 
 // ---------------------------------------------------------------------------
 // small_step: one workgroup of 1024 threads finishes a pass.
@@ -439,23 +449,17 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     }
   }
 
-  // 1. Gramian blocks from the reduced slots (the last reduction stage, in
-  //    group order): B~ = E[0:q, :], G = E[q:q+p, :] (upper, mirrored).
+  // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
+  //    G = E[q:q+p, :] (upper, mirrored).
   const int q4 = (q + 3) & ~3;
   for (int e = tid; e < p * p; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     const int lo = min(i, j), hi = max(i, j);
-    const int64_t idx = e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15);
-    double s = 0.0;
-    for (int gi = 0; gi < a.ngroups; ++gi) s += a.E[(int64_t)gi * a.estride + idx];
-    X[e] = s;
+    X[e] = a.E[e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
   }
   for (int e = tid; e < qp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
-    const int64_t idx = e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15);
-    double s = 0.0;
-    for (int gi = 0; gi < a.ngroups; ++gi) s += a.E[(int64_t)gi * a.estride + idx];
-    Bt[e] = s;
+    Bt[e] = a.E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
   }
   // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2)
   for (int e = tid; e < pp; e += kSmallThreads) {
