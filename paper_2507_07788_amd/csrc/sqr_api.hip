@@ -12,6 +12,8 @@
 #include <stdint.h>
 #include <string.h>
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -29,14 +31,16 @@ constexpr int kMaxSlots = 1024;
 // (3 ld + m) * 8 bytes, below 4 GiB.
 constexpr int64_t kMaxLd = (int64_t)1 << 27;
 constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
-constexpr size_t kSmallLdsBytes = 136 * 1024;  // small_step arena in LDS up to this
+// small_step arena in LDS up to this (its static LDS, about 25 KB, comes on top)
+constexpr size_t kSmallLdsBytes = 128 * 1024;
+size_t g_small_lds = kSmallLdsBytes;
 
 // ---- measurement records (sqr_prof.h) ----
 struct ProfRec { hipEvent_t e0, e1; int kind; double bytes; int64_t call; int phase; int real; };
 std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_event_pool;
 bool g_prof_on = false;
-int64_t g_call_id = 0;
+std::atomic<int64_t> g_call_id{0};
 
 hipEvent_t take_event() {
   if (g_event_pool.empty()) {
@@ -61,14 +65,6 @@ void prof_finalize(int64_t id, int passes) {
 std::mutex g_cache_mu;
 struct CachedWs { void* ptr = nullptr; size_t bytes = 0; int device = -1; void* pinned = nullptr; };
 CachedWs g_cache;
-
-__global__ void init_ctrl(Ctrl* c) {
-  if (threadIdx.x == 0) {
-    c->done = 0; c->status = 0; c->passes = 0; c->chol_attempts = 0;
-    c->converged = 0; c->orth_fro = 0.0;
-  }
-  if (threadIdx.x < 16) c->sigma[threadIdx.x] = 0.0;
-}
 
 int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
 int64_t nblocks(int64_t p) { return (p + 15) / 16; }
@@ -95,7 +91,8 @@ struct sqr_basis {
   int slots = 0;                     // partial-Gram slots (workgroups of block_pass)
   void* ws = nullptr;
   Ctrl* ctrl = nullptr;
-  Ctrl* ctrl_host = nullptr;         // pinned
+  Ctrl* ctrl_host = nullptr;         // pinned, written by small_step
+  Ctrl* ctrl_host_dev = nullptr;     // its device address
   double *part = nullptr, *stage = nullptr;
   double *X = nullptr;
   double *bneg = nullptr, *rinv = nullptr;
@@ -137,8 +134,11 @@ void set_kernel_attributes() {
     (void)hipFuncSetAttribute((const void*)v.gram, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     (void)hipFuncSetAttribute((const void*)v.apply, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
   }
-  (void)hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kSmallLdsBytes);
+  if (hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kSmallLdsBytes) != hipSuccess) {
+    (void)hipGetLastError();   // consumed here: arenas then live in the workspace
+    g_small_lds = 0;
+  }
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -207,10 +207,13 @@ int alloc_workspace(sqr_basis* b) {
   b->bneg = base + o_bneg; b->rinv = base + o_rinv;
   b->ctrl = (Ctrl*)(base + o_ctrl);
   if (!b->ctrl_host &&
-      hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     b->ctrl_host = nullptr; return SQR_EHIP;
   }
   memset(b->ctrl_host, 0, sizeof(Ctrl));
+  if (hipHostGetDevicePointer((void**)&b->ctrl_host_dev, b->ctrl_host, 0) != hipSuccess)
+    return SQR_EHIP;
   return SQR_OK;
 }
 
@@ -256,7 +259,8 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     a.bneg = b->bneg + bneg_off(c.q, J);
     a.rinv = b->rinv + 256 * J;
     a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
-    a.done = &b->ctrl->done; a.passes = &b->ctrl->passes;
+    a.done = phase > 0 ? &b->ctrl->done : nullptr;  // phase 0 starts the call
+    a.passes = &b->ctrl->passes;
     a.copy_if_done = (phase == 1);
     const int ks = (int)round4(a.n1) + a.n2;   // columns of S with the padding
     const Variant* v = pick_variant((ks + 15) / 16);
@@ -280,7 +284,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
   hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 63) / 64)), dim3(64 * kRedWaves), 0, s,
                      (const double*)b->part, (int)nwg, tl, tl, b->stage,
-                     (const int*)&b->ctrl->done);
+                     phase > 0 ? (const int*)&b->ctrl->done : (const int*)nullptr);
   SmallArgs k;
   memset(&k, 0, sizeof(k));
   k.E = b->stage;
@@ -289,20 +293,48 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   k.R = b->R; k.ldr = b->ldr;
   k.X = b->X;
   k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+  k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256;
   k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
   k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
   k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
   const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
-  k.lds_matrices = arena <= kSmallLdsBytes;
+  k.lds_matrices = arena <= g_small_lds;
   hipLaunchKernelGGL(small_step, dim3(1), dim3(kSmallThreads), k.lds_matrices ? arena : 0, s, k);
   return hipGetLastError() == hipSuccess ? SQR_OK : SQR_EHIP;
 }
 
 int fetch(sqr_basis* b, hipStream_t s) {
-  if (hipMemcpyAsync(b->ctrl_host, b->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return SQR_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return SQR_EHIP;
   return SQR_OK;
+}
+
+// Wait until the device has published the outcome of phase `enq` of the
+// current call, or an earlier decision (done).  small_step writes the state
+// into pinned host memory, so the host polls it instead of copying it and
+// waiting for the stream to drain; it still checks the stream now and then
+// for errors, and after kSpinLimit falls back to a blocking stream wait.
+int wait_phase(sqr_basis* b, hipStream_t s, int enq) {
+  constexpr double kSpinLimitUs = 2000.0;
+  volatile Ctrl* h = b->ctrl_host;
+  const int64_t want = b->call_id * 256;
+  auto ready = [&]() {
+    const int64_t st = __atomic_load_n(&b->ctrl_host->stamp, __ATOMIC_ACQUIRE);
+    return st >= want && st < want + 256 && (h->done || st - want >= enq);
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int it = 1;; ++it) {
+    if (ready()) return SQR_OK;
+    if ((it & 1023) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e != hipSuccess && e != hipErrorNotReady) return SQR_EHIP;
+      const double us = std::chrono::duration<double, std::micro>(
+                            std::chrono::steady_clock::now() - t0).count();
+      if (e == hipSuccess || us > kSpinLimitUs) break;
+    }
+    __builtin_ia32_pause();
+  }
+  if (fetch(b, s)) return SQR_EHIP;
+  return ready() ? SQR_OK : SQR_EHIP;
 }
 
 void fill_info(const Ctrl* c, sqr_info* info) {
@@ -319,7 +351,6 @@ void fill_info(const Ctrl* c, sqr_info* info) {
 int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   b->stream = s;
   b->call_id = ++g_call_id;
-  hipLaunchKernelGGL(init_ctrl, dim3(1), dim3(64), 0, s, b->ctrl);
   int rc = launch_gram(b, c, 0, s);
   if (rc) return rc;
   const int maxit = b->opts.max_iter;
@@ -328,14 +359,10 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   for (; enq < first; ++enq)
     if ((rc = launch_gram(b, c, enq + 1, s))) return rc;
   if (!sync) return SQR_OK;
-  if ((rc = fetch(b, s))) return rc;
+  if ((rc = wait_phase(b, s, enq))) return rc;
   while (!b->ctrl_host->done && enq < maxit) {
     if ((rc = launch_gram(b, c, ++enq, s))) return rc;
-    if ((rc = fetch(b, s))) return rc;
-  }
-  if (!b->ctrl_host->done) {
-    // all passes enqueued; the last small_step has decided
-    if ((rc = fetch(b, s))) return rc;
+    if ((rc = wait_phase(b, s, enq))) return rc;
   }
   if (g_prof_on) prof_finalize(b->call_id, b->ctrl_host->passes);
   return SQR_OK;

@@ -22,6 +22,8 @@ struct Ctrl {
   int32_t pad[3];
   double orth_fro;        // last ||X - I||_F
   double sigma[16];       // shift of each pass (0 = unshifted)
+  int64_t stamp;          // host copy only: call id * 256 + phase of the last
+                          // small_step that published this state
 };
 
 // One launch of block_pass: 16-column block J of a pass.
@@ -35,7 +37,7 @@ struct BlockPassArgs {
   const double* bneg;                 // (n1+n2 rounded up to 4) x 16, row-major: -B~_J
   const double* rinv;                 // 16 x 16 row-major inverse of the diagonal block
   double* part; int64_t part_stride; int64_t part_off;  // slot b at part + b*stride + off
-  const int32_t* done;
+  const int32_t* done;                // NULL in the initial Gram pass of a call
   const int32_t* passes;
   int32_t copy_if_done;
 };
@@ -58,6 +60,8 @@ struct SmallArgs {
   double* bneg;          // per block J: (q + 16J rounded up to 4) x 16, row-major
   double* rinv;          // per block J: 16 x 16
   Ctrl* ctrl;
+  Ctrl* hctrl;           // pinned host mirror (device address), or NULL
+  int64_t stamp_base;    // call id * 256
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
   double tol, u;

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   const int64_t t0 = (int64_t)blockIdx.x * per;
   const int64_t t1 = min(tiles, t0 + per);
 
-  if (*a.done) {
+  if (a.done && *a.done) {
     // A finished call: nothing to do, except that the first apply of a call
     // that converged before any pass copies the input block to the output.
     if (APPLY && a.copy_if_done && *a.passes == 0) {
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __r
                                                              double* __restrict__ out,
                                                              const int* done) {
   __shared__ double part[kRedWaves][64];
-  if (*done) return;
+  if (done && *done) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
@@ -367,13 +367,26 @@ constexpr int kSmallWaves = kSmallThreads / 64;
 
 // Deterministic workgroup sum: a fixed butterfly inside each wave, then the
 // wave sums in wave order.  Every thread gets the result.
-__device__ double block_sum(double v, double* buf) {
+// Workgroup barrier.  lds_only: order LDS accesses only, so global stores in
+// flight are not waited for (small_step keeps its matrices in LDS and orders
+// its few global read-after-write hand-offs with full barriers).
+__device__ __forceinline__ void wg_sync(bool lds_only) {
+  if (lds_only) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
+
+__device__ double block_sum(double v, double* buf, bool lds_only) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int wv = threadIdx.x >> 6;
-  __syncthreads();
+  wg_sync(lds_only);
   if ((threadIdx.x & 63) == 0) buf[wv] = v;
-  __syncthreads();
+  wg_sync(lds_only);
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < kSmallWaves; ++i) s += buf[i];
@@ -389,25 +402,52 @@ __device__ __forceinline__ int64_t e_off(int q4, int J) {
 
 // In-place upper Cholesky of the row-major p x p matrix M (right-looking).
 // Returns false on breakdown: a pivot that is not > 0 or not finite.
-__device__ bool chol_upper(double* M, int p) {
+__device__ bool chol_upper(double* M, int p, bool lds_only) {
   const int tid = threadIdx.x;
   for (int j = 0; j < p; ++j) {
-    __syncthreads();
+    wg_sync(lds_only);
     const double d = M[(int64_t)j * p + j];
     if (!(d > 0.0) || !isfinite(d)) return false;  // uniform: all read d
     const double r = sqrt(d);
-    __syncthreads();
+    wg_sync(lds_only);
     if (tid == 0) M[(int64_t)j * p + j] = r;
     for (int k = j + 1 + tid; k < p; k += kSmallThreads) M[(int64_t)j * p + k] /= r;
-    __syncthreads();
+    wg_sync(lds_only);
     const int w = p - j - 1;
     for (int e = tid; e < w * w; e += kSmallThreads) {
       const int i = j + 1 + e / w, k = j + 1 + e % w;
       if (k >= i) M[(int64_t)i * p + k] -= M[(int64_t)j * p + i] * M[(int64_t)j * p + k];
     }
   }
-  __syncthreads();
+  wg_sync(lds_only);
   return true;
+}
+
+// The same factorisation by wave 0 alone for p <= 64 (no workgroup barriers;
+// LDS hand-offs within the wave).  Every thread receives the outcome.
+__device__ bool chol_upper_wave(double* M, int p, int* flag) {
+  const int tid = threadIdx.x;
+  wg_sync(true);
+  if (tid < 64) {
+    bool ok = true;
+    for (int j = 0; j < p; ++j) {
+      const double d = M[(int64_t)j * p + j];
+      if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }  // uniform in the wave
+      const double r = sqrt(d);
+      for (int k = j + 1 + tid; k < p; k += 64) M[(int64_t)j * p + k] /= r;
+      wave_lds_sync();
+      if (tid == 0) M[(int64_t)j * p + j] = r;
+      const int w = p - j - 1;
+      for (int e = tid; e < w * w; e += 64) {
+        const int i = j + 1 + e / w, k = j + 1 + e % w;
+        if (k >= i) M[(int64_t)i * p + k] -= M[(int64_t)j * p + i] * M[(int64_t)j * p + k];
+      }
+      wave_lds_sync();
+    }
+    if (tid == 0) *flag = ok ? 1 : 0;
+  }
+  wg_sync(true);
+  return *flag != 0;
 }
 
 // Doubles small_step keeps in LDS when they fit: X, M, R_old (p x p each),
@@ -417,13 +457,52 @@ __host__ __device__ inline int64_t small_arena(int q, int p) {
   return 3 * pp + qp + (qp > pp ? qp : pp);
 }
 
+// Write this small_step's outcome to the pinned host mirror, then its stamp
+// (call id and phase), so a host that sees the stamp also sees the state.
+// Fields not passed keep the values earlier phases of the call wrote; phase 0
+// starts from a cleared mirror.  Thread 0 only.
+struct Outcome {
+  int done, status, converged;
+  int passes, attempts;     // < 0: unchanged
+  int sigma_idx;            // < 0: unchanged
+  double sigma, orth_fro;
+};
+__device__ void publish(const SmallArgs& a, const Outcome& o) {
+  Ctrl* h = a.hctrl;
+  if (!h) return;
+  if (a.phase == 0) {
+    h->passes = 0; h->chol_attempts = 0;
+    for (int i = 0; i < 16; ++i) h->sigma[i] = 0.0;
+  }
+  h->done = o.done; h->status = o.status; h->converged = o.converged;
+  if (o.passes >= 0) h->passes = o.passes;
+  if (o.attempts >= 0) h->chol_attempts = o.attempts;
+  if (o.sigma_idx >= 0 && o.sigma_idx < 16) h->sigma[o.sigma_idx] = o.sigma;
+  h->orth_fro = o.orth_fro;
+  __threadfence_system();
+  __hip_atomic_store(&h->stamp, a.stamp_base + a.phase, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[kSmallWaves];
   __shared__ double v[kMaxCols], w[kMaxCols];
+  __shared__ double dls[4 * 256];    // inverted diagonal blocks (p <= 64)
+  __shared__ int cflag;
   Ctrl* c = a.ctrl;
-  if (c->done) return;
   const int tid = threadIdx.x;
+  const bool lo = a.lds_matrices != 0;   // matrices in LDS: LDS-only barriers
+  int prev_att = 0;  // factorisations of earlier passes (thread 0)
+  if (a.phase > 0) {
+    if (c->done) return;
+    if (tid == 0) prev_att = c->chol_attempts;
+  } else if (tid == 0) {
+    // first small_step of a call: fresh state
+    c->done = 0; c->status = 0; c->passes = 0; c->chol_attempts = 0;
+    c->converged = 0; c->orth_fro = 0.0;
+    for (int i = 0; i < 16; ++i) c->sigma[i] = 0.0;
+  }
   const int p = a.p, q = a.q;
   const int64_t pp = (int64_t)p * p, qp = (int64_t)q * p;
   double* base = a.lds_matrices ? lds : a.X;   // arena (LDS, or workspace)
@@ -431,7 +510,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   double* M = X + pp;
   double* Ro = M + pp;          // old diagonal block of R (row-major)
   double* Bt = Ro + pp;         // B~ (row-major q x p)
-  double* Rn = Bt + qp;         // scratch
+  double* Bo = Bt + qp;         // B before this pass (append), q x p
   double* R = a.R;
   const int64_t ldr = a.ldr;
   const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
@@ -461,21 +540,54 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     const int i = e / p, j = e % p;
     Bt[e] = a.E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
   }
-  // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2)
+  // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2) and
+  // old B (zero at phase 0), loaded together with the Gramian blocks
   for (int e = tid; e < pp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     Ro[e] = (a.phase == 0) ? (i == j ? 1.0 : 0.0) : R[roff + i + (int64_t)j * ldr];
   }
-  __syncthreads();
-  // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
-  if (a.mode == 1 && q > 0) {
-    for (int e = tid; e < pp; e += kSmallThreads) {
+  if (a.mode == 1) {
+    for (int e = tid; e < qp; e += kSmallThreads) {
       const int i = e / p, j = e % p;
-      double s = 0.0;
-      for (int k = 0; k < q; ++k) s += Bt[(int64_t)k * p + i] * Bt[(int64_t)k * p + j];
-      X[e] -= s;
+      Bo[e] = (a.phase == 0) ? 0.0 : R[i + (int64_t)(q + j) * ldr];
     }
-    __syncthreads();
+  }
+  // phase 0: the stores of R above precede the stores of step 6 by other threads
+  wg_sync(lo && a.phase > 0);
+  // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
+  //    Upper triangle, each sum split over kSplit interleaved k-ranges whose
+  //    partial sums are added in a fixed order; mirrored to the lower part.
+  if (a.mode == 1 && q > 0) {
+    constexpr int kSplit = 4;
+    const bool split = pp * kSplit <= kMaxCols;
+    const int S = split ? kSplit : 1;
+    for (int t = tid; t < pp * S; t += kSmallThreads) {
+      const int e = t / S, sg = t % S;
+      const int i = e / p, j = e % p;
+      if (i > j) continue;
+      double s = 0.0;
+#pragma unroll 8
+      for (int k = sg; k < q; k += S) s += Bt[(int64_t)k * p + i] * Bt[(int64_t)k * p + j];
+      if (split) {
+        v[t] = s;
+      } else {
+        X[e] -= s;
+        if (i != j) X[(int64_t)j * p + i] -= s;
+      }
+    }
+    wg_sync(lo);
+    if (split) {
+      for (int e = tid; e < pp; e += kSmallThreads) {
+        const int i = e / p, j = e % p;
+        if (i > j) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int sg = 0; sg < kSplit; ++sg) s += v[e * kSplit + sg];
+        X[e] -= s;
+        if (i != j) X[(int64_t)j * p + i] -= s;
+      }
+      wg_sync(lo);
+    }
   }
   // 3. ||X - I||_F.
   double part = 0.0;
@@ -484,7 +596,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     const double d = X[e] - (i == j ? 1.0 : 0.0);
     part += d * d;
   }
-  const double err = sqrt(block_sum(part, red));
+  const double err = sqrt(block_sum(part, red, lo));
   // 4. Stopping test (Algorithm 1 with the CholQR3 start; Algorithm 2).
   int status = -1;
   if (!isfinite(err)) {
@@ -500,6 +612,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       c->converged = (status == 0);
       c->orth_fro = err;
       c->done = 1;
+      publish(a, Outcome{1, status, status == 0, -1, -1, -1, 0.0, err});
     }
     return;
   }
@@ -512,31 +625,32 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   if (!shifted) {
     for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
     ++attempts;
-    ok = chol_upper(M, p);
+    ok = (p <= 64 && a.lds_matrices) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, lo);
     shifted = !ok;
   }
   if (shifted) {
     // ||X||_2 by power iteration from the all-ones vector.
     for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
-    __syncthreads();
+    wg_sync(lo);
     double lam = 0.0;
     bool early = false;
     for (int s = 0; s < a.power_steps; ++s) {
       double pp2 = 0.0;
       for (int i = tid; i < p; i += kSmallThreads) {
         double t = 0.0;
+#pragma unroll 8
         for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
         w[i] = t;
         pp2 += t * t;
       }
-      const double nrm = sqrt(block_sum(pp2, red));
+      const double nrm = sqrt(block_sum(pp2, red, lo));
       if (!(nrm > 0.0) || !isfinite(nrm)) {
         lam = isfinite(nrm) ? nrm : __builtin_nan("");
         early = true;
         break;
       }
       for (int i = tid; i < p; i += kSmallThreads) v[i] = w[i] / nrm;
-      __syncthreads();
+      wg_sync(lo);
     }
     if (!early) {
       double pp2 = 0.0;
@@ -545,7 +659,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
         for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
         pp2 += v[i] * t;
       }
-      lam = fabs(block_sum(pp2, red));
+      lam = fabs(block_sum(pp2, red, lo));
     }
     const double mm = (double)a.m;
     const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
@@ -555,7 +669,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       for (int e = tid; e < pp; e += kSmallThreads)
         M[e] = X[e] + ((e / p == e % p) ? sigma : 0.0);
       ++attempts;
-      ok = chol_upper(M, p);
+      ok = (p <= 64 && a.lds_matrices) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, lo);
       if (ok) break;
       if (esc >= a.max_escalations) break;
       sigma = fmax(10.0 * sigma, 2.0 * a.u);
@@ -563,76 +677,128 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     if (!ok) {
       if (tid == 0) {
         c->status = 2;  // SQR_BREAKDOWN
-        c->chol_attempts += attempts;
+        c->chol_attempts = prev_att + attempts;
         c->orth_fro = err;
         c->done = 1;
+        publish(a, Outcome{1, 2, 0, -1, prev_att + attempts, -1, 0.0, err});
       }
       return;
     }
   }
-  __syncthreads();
+  wg_sync(lo);
   // 6. B <- B + B~ R_old, then R <- R~ R_old (Algorithm 2; Algorithm 1).
+  //    Fixed trip counts for p <= 16 (one row of B per thread, the row of
+  //    B~ in registers; stores along columns of R coalesce).
   if (a.mode == 1 && q > 0) {
-    for (int e = tid; e < qp; e += kSmallThreads) {
-      const int i = e / p, j = e % p;
-      double s = 0.0;
-      for (int k = 0; k <= j; ++k) s += Bt[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
-      R[i + (int64_t)(q + j) * ldr] += s;
+    if (p <= 16) {
+      for (int i = tid; i < q; i += kSmallThreads) {
+        double br[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) br[k] = (k < p) ? Bt[(int64_t)i * p + k] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j < p) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k <= j; ++k) s += br[k] * Ro[(int64_t)k * p + j];
+            R[i + (int64_t)(q + j) * ldr] = Bo[(int64_t)i * p + j] + s;
+          }
+        }
+      }
+    } else {
+      for (int e = tid; e < qp; e += kSmallThreads) {
+        const int i = e / p, j = e % p;
+        double s = 0.0;
+#pragma unroll 4
+        for (int k = 0; k <= j; ++k) s += Bt[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+        R[i + (int64_t)(q + j) * ldr] = Bo[e] + s;
+      }
     }
   }
   for (int e = tid; e < pp; e += kSmallThreads) {
     const int i = e / p, j = e % p;
     double s = 0.0;
-    for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+    if (p <= 16) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k >= i && k <= j) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+    } else {
+#pragma unroll 4
+      for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+    }
     R[roff + i + (int64_t)j * ldr] = (i <= j) ? s : 0.0;
   }
   // 7. Operands of the next pass.  D_J = inverse of the diagonal block J of
   //    R~ (identity beyond p), by back substitution on each column.
+  //    Fixed trip counts (masked beyond column cc) let every load of the
+  //    block issue ahead of the dependent arithmetic.
   for (int t = tid; t < a.nblk * 16; t += kSmallThreads) {
     const int J = t >> 4, cc = t & 15, b0 = 16 * J;
     const int pb = min(16, p - b0);
     double col[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) col[i] = 0.0;
     if (cc >= pb) {
-      col[cc] = 1.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) col[i] = (i == cc) ? 1.0 : 0.0;
     } else {
-      for (int i = cc; i >= 0; --i) {
+      const double* Mb = M + (int64_t)b0 * p + b0;
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
         double s = (i == cc) ? 1.0 : 0.0;
-        for (int k = i + 1; k <= cc; ++k) s -= M[(int64_t)(b0 + i) * p + b0 + k] * col[k];
-        col[i] = s / M[(int64_t)(b0 + i) * p + b0 + i];
+#pragma unroll
+        for (int k = i + 1; k < 16; ++k)
+          if (k <= cc) s -= Mb[(int64_t)i * p + k] * col[k];
+        if (i <= cc)
+          col[i] = s / Mb[(int64_t)i * p + i];
+        else
+          col[i] = 0.0;
       }
     }
     double* rv = a.rinv + J * 256;
 #pragma unroll
     for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
+    if (a.nblk <= 4) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dls[J * 256 + i * 16 + cc] = col[i];
+    }
   }
-  __syncthreads();  // D_J complete (global, this workgroup)
+  wg_sync(lo && a.nblk <= 4);  // D_J complete (LDS, or global beyond 4 blocks)
   //    C_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]] D_J, so the
   //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
+  //    One row of C_J per thread: the row of the source in registers, D_J
+  //    read as broadcasts.
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
     const int rows = q4 + b0;
-    const double* D = a.rinv + J * 256;
+    const double* D = (a.nblk <= 4) ? dls + J * 256 : a.rinv + J * 256;
     double* bn = a.bneg + 16 * ((int64_t)J * q4 + 8 * (int64_t)J * (J - 1));
-    for (int e = tid; e < rows * 16; e += kSmallThreads) {
-      const int kk = e >> 4, cc = e & 15;
-      double val = 0.0;
-      if (cc < pb && (kk < q || kk >= q4)) {
-        for (int t = 0; t <= cc; ++t) {
-          const double src = (kk < q) ? Bt[(int64_t)kk * p + b0 + t]
-                                      : M[(int64_t)(kk - q4) * p + b0 + t];
-          val -= src * D[t * 16 + cc];
+    for (int kk = tid; kk < rows; kk += kSmallThreads) {
+      double src[16];
+      const bool real = kk < q || kk >= q4;
+      const double* sr = (kk < q) ? Bt + (int64_t)kk * p + b0
+                                  : (real ? M + (int64_t)(kk - q4) * p + b0 : Bt);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) src[t] = (real && t < pb) ? sr[t] : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 16; cc += 2) {
+        double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+        for (int t = 0; t <= cc + 1; ++t) {
+          if (t <= cc) v0 -= src[t] * D[t * 16 + cc];
+          v1 -= src[t] * D[t * 16 + cc + 1];
         }
+        double2 o;
+        o.x = (cc < pb) ? v0 : 0.0;
+        o.y = (cc + 1 < pb) ? v1 : 0.0;
+        *reinterpret_cast<double2*>(bn + (int64_t)kk * 16 + cc) = o;
       }
-      bn[e] = val;
     }
   }
   if (tid == 0) {
     c->passes = pass;
     if (pass <= 16) c->sigma[pass - 1] = sigma;
-    c->chol_attempts += attempts;
+    c->chol_attempts = prev_att + attempts;
     c->orth_fro = err;
+    publish(a, Outcome{0, 0, 0, pass, prev_att + attempts, pass - 1, sigma, err});
   }
 }
 
