@@ -78,9 +78,13 @@ void sqr_default_opts(sqr_opts* o);
  *   R, ldr   cap x cap output, ldr >= cap; R[0:n, 0:n] receives the upper
  *            triangular factor, its strictly lower part is written as zero.
  *   stream   hipStream_t to run on (NULL = the null stream).
- *   info     host struct, or NULL.  Non-NULL: the call synchronises the
- *            stream and returns the numerical status.  NULL: the call returns
- *            after enqueueing; fetch the outcome later with sqr_last_info.
+ *   info     host struct, or NULL.  Non-NULL: the call waits until the
+ *            device has decided the outcome (it publishes it to pinned host
+ *            memory) and returns the numerical status; kernels of the call
+ *            that have nothing left to do may still be queued, so Q and R are
+ *            complete for later work on `stream`, and for the host or other
+ *            streams once `stream` is synchronised.  NULL: the call returns
+ *            after enqueueing; sqr_last_info synchronises and reports.
  *
  * Ownership: A, Q and R are borrowed and must stay allocated until the work
  * enqueued on `stream` completes.  The handle owns only its workspace.
@@ -97,8 +101,9 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
  * columns of W (m x p, ldw >= m), writing the new columns to Q[:, n:n+p] and
  * R[0:n+p, n:n+p] (B above R, Prop. 2.1).  On SQR_OK the handle's n grows by
  * p.  On any non-zero status n is unchanged (the reserved columns may hold
- * partial results).  W is read only.  Always synchronises `stream` (the new
- * width depends on the outcome); `info` may be NULL.
+ * partial results).  W is read only.  Always waits for the outcome, as
+ * sqr_orth does with a non-NULL info (the new width depends on it); `info`
+ * may be NULL.
  * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^27, n + p > cap,
  * n + p > m).
  */

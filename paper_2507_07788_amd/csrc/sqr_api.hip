@@ -114,6 +114,19 @@ const Variant kVariants[] = {
 };
 #undef SQR_VARIANT
 
+// Whole-pass kernels of orth calls with 2..8 column blocks.
+typedef void (*WideKernel)(WidePassArgs);
+struct WideVariant { WideKernel gram, apply; };
+#define SQR_WIDE(NB) {wide_pass<NB, false>, wide_pass<NB, true>}
+constexpr int kWideMin = 2, kWideMax = 8;
+const WideVariant kWide[] = {SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4), SQR_WIDE(5),
+                             SQR_WIDE(6), SQR_WIDE(7), SQR_WIDE(8)};
+#undef SQR_WIDE
+int g_wide_occ[2][kWideMax - kWideMin + 1];
+size_t wide_lds_bytes(int nb, bool apply) {
+  return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));
+}
+
 // Smallest variant whose S capacity covers ns tiles (listed by capacity).
 const Variant* pick_variant(int ns) {
   for (const Variant& v : kVariants)
@@ -139,6 +152,13 @@ void set_kernel_attributes() {
     (void)hipGetLastError();   // consumed here: arenas then live in the workspace
     g_small_lds = 0;
   }
+  for (int nb = kWideMin; nb <= kWideMax; ++nb)
+    for (int ap = 0; ap < 2; ++ap) {
+      const WideKernel k = ap ? kWide[nb - kWideMin].apply : kWide[nb - kWideMin].gram;
+      (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)wide_lds_bytes(nb, ap != 0));
+    }
+  (void)hipGetLastError();
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -156,6 +176,16 @@ void set_kernel_attributes() {
     }
     ++i;
   }
+  for (int nb = kWideMin; nb <= kWideMax; ++nb)
+    for (int ap = 0; ap < 2; ++ap) {
+      const WideKernel k = ap ? kWide[nb - kWideMin].apply : kWide[nb - kWideMin].gram;
+      int n = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k, kThreads,
+                                                        wide_lds_bytes(nb, ap != 0)) != hipSuccess ||
+          n < 1)
+        n = 1;
+      g_wide_occ[ap][nb - kWideMin] = n;
+    }
   g_attr_done = true;
 }
 
@@ -231,10 +261,45 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   const int64_t tl = total_len(c.q, c.p);
   const int64_t tiles = (b->m + 15) / 16;
   const bool apply = phase > 0;
+  int64_t nwg = b->slots;
+  if (c.mode == 0 && P >= kWideMin && P <= kWideMax) {
+    // the whole pass in one launch
+    const int idx = (int)P - kWideMin;
+    const int64_t steps = (tiles + kWaves - 1) / kWaves;
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_wide_occ[apply ? 1 : 0][idx]);
+    nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, steps));
+    WidePassArgs w;
+    memset(&w, 0, sizeof(w));
+    w.win = (apply && phase > 1) ? c.y : c.win;
+    w.ldw = (apply && phase > 1) ? c.ldy : c.ldw;
+    w.yout = c.y; w.ldy = c.ldy;
+    w.n = (int)c.p; w.m = b->m;
+    w.bneg = b->bneg; w.rinv = b->rinv;
+    w.part = b->part; w.part_stride = tl;
+    w.done = phase > 0 ? &b->ctrl->done : nullptr;
+    w.passes = &b->ctrl->passes;
+    w.copy_if_done = (phase == 1);
+    void* args[] = {&w};
+    ProfRec rec{};
+    if (g_prof_on) {
+      rec.e0 = take_event(); rec.e1 = take_event();
+      rec.kind = apply ? 1 : 0;
+      rec.bytes = 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0);
+      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
+      if (rec.e0) (void)hipEventRecord(rec.e0, s);
+    }
+    const WideKernel k = apply ? kWide[idx].apply : kWide[idx].gram;
+    if (hipLaunchKernel((const void*)k, dim3((unsigned)nwg), dim3(kThreads), args,
+                        wide_lds_bytes((int)P, apply), s) != hipSuccess)
+      return SQR_EHIP;
+    if (g_prof_on && rec.e0 && rec.e1) {
+      (void)hipEventRecord(rec.e1, s);
+      g_prof.push_back(rec);
+    }
+  } else {
   // One grid size for every block of the pass (the slots are reduced
   // together): resident workgroups of the most demanding block's variant,
   // capped by the slot capacity and by the row tiles available.
-  int64_t nwg = b->slots;
   for (int64_t J = 0; J < P; ++J) {
     const int ks = (int)round4(c.q) + (int)(16 * J);
     const Variant* v = pick_variant((ks + 15) / 16);
@@ -280,6 +345,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       (void)hipEventRecord(rec.e1, s);
       g_prof.push_back(rec);
     }
+  }
   }
   // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
   hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 63) / 64)), dim3(64 * kRedWaves), 0, s,

@@ -42,6 +42,20 @@ struct BlockPassArgs {
   int32_t copy_if_done;
 };
 
+// One launch of wide_pass: a whole pass of an orth call with 2..8 blocks.
+struct WidePassArgs {
+  const double* win;  int64_t ldw;   // input (m x n)
+  double* yout;       int64_t ldy;   // output (apply mode; may equal win)
+  int32_t n;                          // columns, 16 (NB - 1) < n <= 16 NB
+  int64_t m;
+  const double* bneg;                 // C_J of each block, row-major (16 J x 16)
+  const double* rinv;                 // D_J of each block, 16 x 16 row-major
+  double* part; int64_t part_stride;  // slot b at part + b * part_stride
+  const int32_t* done;                // NULL in the initial Gram pass of a call
+  const int32_t* passes;
+  int32_t copy_if_done;
+};
+
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
   const double* E;       // reduced partial Gramians of the pass, block after block

@@ -359,6 +359,184 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __r
   }
 }
 
+// Offset (in doubles) of block J's partial Gramian inside a reduced slot:
+// block J' holds (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4
+// (rows q..q4-1 belong to the zero padding of S and are ignored).
+__device__ __forceinline__ int64_t e_off(int q4, int J) {
+  return 16 * ((int64_t)J * (q4 + 16) + 8 * (int64_t)J * (J - 1));
+}
+
+// ---------------------------------------------------------------------------
+// wide_pass: one launch per pass of an orth call whose n columns form NB
+// blocks (2 <= NB <= 8).  Same arithmetic as the per-block launches
+// (Y_J = W_J D_J + sum_{I<J} Y_I C_IJ, then the Gramian of Y), but a wave
+// keeps the Y blocks of its 16-row tile in registers, so the prefix Y_<J is
+// never re-read from HBM: the pass reads W once and writes Y once.
+//
+// Workgroup: four waves, one 16-row tile each (64 rows per step).  LDS holds
+// the operands of the pass (per block J the panel [C_J; D_J], row-major, 16
+// columns) and, per step, the transposed Y tiles of all four waves in MFMA
+// operand order; each wave then accumulates the Gramian blocks (I, J) it
+// owns (pairs dealt out round-robin) over the 64 rows.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int wide_panel_doubles(int nb) { return 128 * nb * (nb + 1); }
+constexpr int kOpSlot = 68;   // one 4 x 16 operand slot, rows padded to 17
+__host__ __device__ constexpr int wide_op_doubles(int nb) { return kWaves * nb * 4 * kOpSlot; }
+
+template <int NB, bool APPLY>
+__global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
+  extern __shared__ double lds[];
+  constexpr int NP = NB * (NB + 1) / 2;           // Gramian blocks (I <= J)
+  constexpr int KP = (NP + kWaves - 1) / kWaves;   // blocks per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t s1 = min(steps, s0 + per);
+
+  if (a.done && *a.done) {
+    if (APPLY && a.copy_if_done && *a.passes == 0) {
+      for (int64_t t = s0 * kWaves + wave; t < min(tiles, s1 * kWaves); t += kWaves) {
+        const int64_t row = t * 16 + x;
+        if (row >= a.m) continue;
+        for (int c = g; c < a.n; c += 4)
+          a.yout[(int64_t)c * a.ldy + row] = a.win[(int64_t)c * a.ldw + row];
+      }
+    }
+    return;
+  }
+
+  double* panel = lds;                                   // APPLY only
+  double* op = lds + (APPLY ? wide_panel_doubles(NB) : 0);
+  if (APPLY) {
+    for (int J = 0; J < NB; ++J) {
+      double* P = panel + 128 * J * (J + 1);
+      const double* C = a.bneg + 128 * J * (J - 1);
+      for (int e = threadIdx.x; e < 256 * J; e += kThreads) P[e] = C[e];
+      for (int e = threadIdx.x; e < 256; e += kThreads) P[256 * J + e] = a.rinv[256 * J + e];
+    }
+  }
+
+  // Input of one tile in D layout: lane (x, g) register r of block J holds
+  // W[row x][16 J + g + 4 r]; columns past n read zero (buffer range), rows
+  // past m are masked.
+  auto load_w = [&](int64_t tile, d4 (&w)[NB]) {
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = row < a.m;
+    const int64_t rowc = row_ok ? row : a.m - 1;
+    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c0 = 16 * J + 4 * r;
+        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+        const uint64_t bits = __builtin_bit_cast(uint64_t,
+            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+        w[J][r] = __builtin_bit_cast(double, bits & keep);
+      }
+  };
+
+  d4 acc[KP];
+  int pi[KP], pj[KP];   // owned Gramian blocks (I, J), I <= J
+  bool pidx_ok[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    const int pidx = wave + kWaves * k;
+    pidx_ok[k] = pidx < NP;
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= pidx && J < NB - 1) ++J;
+    pj[k] = J;
+    pi[k] = min(pidx - J * (J + 1) / 2, J);
+  }
+
+  d4 wnext[NB];
+  load_w(min(s0 * kWaves + wave, tiles - 1), wnext);
+  __syncthreads();  // panels loaded
+  double* myop = op + wave * NB * 4 * kOpSlot;
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t tile = s * kWaves + wave;
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = tile < tiles && row < a.m;
+    d4 y[NB];
+#pragma unroll
+    for (int J = 0; J < NB; ++J) y[J] = wnext[J];
+    load_w(min(tile + kWaves, tiles - 1), wnext);
+    if (!APPLY && !row_ok) {
+#pragma unroll
+      for (int J = 0; J < NB; ++J) y[J] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    if (APPLY) {
+#pragma unroll
+      for (int J = 0; J < NB; ++J) {
+        const double* P = panel + 128 * J * (J + 1);
+        d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
+        d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
+        // W_J D_J (block J of y still holds W_J)
+        c0 = mfma(P[(16 * J + g) * 16 + x], y[J][0], c0);
+        c1 = mfma(P[(16 * J + 4 + g) * 16 + x], y[J][1], c1);
+        c0 = mfma(P[(16 * J + 8 + g) * 16 + x], y[J][2], c0);
+        c1 = mfma(P[(16 * J + 12 + g) * 16 + x], y[J][3], c1);
+        // + Y_I C_IJ for the finished blocks I < J
+#pragma unroll
+        for (int I = 0; I < J; ++I) {
+          c0 = mfma(P[(16 * I + g) * 16 + x], y[I][0], c0);
+          c1 = mfma(P[(16 * I + 4 + g) * 16 + x], y[I][1], c1);
+          c0 = mfma(P[(16 * I + 8 + g) * 16 + x], y[I][2], c0);
+          c1 = mfma(P[(16 * I + 12 + g) * 16 + x], y[I][3], c1);
+        }
+        y[J] = row_ok ? (c0 + c1) : d4{0.0, 0.0, 0.0, 0.0};
+        if (row_ok) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = 16 * J + g + 4 * r;
+            if (col < a.n) a.yout[(int64_t)col * a.ldy + row] = y[J][r];
+          }
+        }
+      }
+    }
+    // Operand order for the Gramian: slot (J, u) holds Y[row 4u + g'][16 J + c]
+    // of this wave's tile at g' * 17 + c (padded rows: the transposing
+    // stores and the operand loads both spread over the LDS banks).
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = y[J][r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (pidx_ok[k]) {
+        const double* oa = op + pi[k] * 4 * kOpSlot + x + 17 * g;
+        const double* ob = op + pj[k] * 4 * kOpSlot + x + 17 * g;
+#pragma unroll
+        for (int t = 0; t < kWaves; ++t)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // Slot: block J holds rows 0..16J+15 of Gramian columns 16J..16J+15.
+  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (pidx_ok[k]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // small_step: one workgroup of 1024 threads finishes a pass.
 // ---------------------------------------------------------------------------
@@ -393,12 +571,6 @@ __device__ double block_sum(double v, double* buf, bool lds_only) {
   return s;
 }
 
-// Offset (in doubles) of block J's partial Gramian inside a reduced slot:
-// block J' holds (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4
-// (rows q..q4-1 belong to the zero padding of S and are ignored).
-__device__ __forceinline__ int64_t e_off(int q4, int J) {
-  return 16 * ((int64_t)J * (q4 + 16) + 8 * (int64_t)J * (J - 1));
-}
 
 // In-place upper Cholesky of the row-major p x p matrix M (right-looking).
 // Returns false on breakdown: a pivot that is not > 0 or not finite.

@@ -47,6 +47,60 @@ def test_matrix(m: int, n: int, kappa: float, seed=(0,)) -> np.ndarray:
     return np.asfortranarray((U * s) @ V.T)
 
 
+def test_matrix_device(m: int, n: int, kappa: float, seed=(0,), device="cuda",
+                       max_elems: int = (1 << 31) - 1):
+    """The same recipe drawn and formed on a GPU, for sizes the host cannot
+    hold comfortably (m up to 2e7): torch's Gaussian generator seeded from
+    SeedSequence(seed, m, n, kappa), Householder QR (torch.linalg.qr) for the
+    orthonormal factors, GEMMs for U diag(s) V^T.  Returns an m x n FP64
+    column-major tensor (a transposed view of an n x m contiguous tensor).
+    Not bit-identical to test_matrix (a different random stream).
+
+    The QR and GEMM libraries behind torch index with 32-bit integers, so no
+    operand handed to them exceeds 2^31 elements: the tall factor U is a
+    two-level Householder QR over row blocks (QR of each block, QR of the
+    stacked R factors, Q_i times its piece of the second Q), and the product
+    is formed block by block (max_elems bounds every operand)."""
+    import torch
+    key = np.random.SeedSequence([int(k) for k in seed] + [m, n, int(round(math.log10(kappa) * 100))])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(key.generate_state(1, dtype=np.uint64)[0] >> np.uint64(1)))
+    f64 = torch.float64
+    lim = max_elems
+
+    def house(G):
+        assert G.numel() <= lim
+        Q, R = torch.linalg.qr(G)
+        return Q, R
+
+    V, Rv = house(torch.randn((n, n), generator=gen, device=device, dtype=f64))
+    dv = torch.sign(torch.diagonal(Rv))
+    dv[dv == 0] = 1.0
+    V = V * dv
+    s = torch.as_tensor(singular_values(n, kappa), device=device, dtype=f64)
+    SVt = (s[:, None] * V.t()).contiguous()          # diag(s) V^T, n x n
+
+    rows = max(n, min(m, lim // max(n, 1)))           # rows per block
+    starts = list(range(0, m, rows))
+    Qs, Rs = [], []
+    for r0 in starts:
+        r1 = min(m, r0 + rows)
+        Qi, Ri = house(torch.randn((r1 - r0, n), generator=gen, device=device, dtype=f64))
+        Qs.append(Qi)
+        Rs.append(Ri)
+    Q2, R2 = house(torch.cat(Rs, 0))                  # (blocks * n) x n
+    d = torch.sign(torch.diagonal(R2))
+    d[d == 0] = 1.0
+    out = torch.empty((n, m), device=device, dtype=f64).t()
+    for i, r0 in enumerate(starts):
+        r1 = min(m, r0 + rows)
+        Ui = Qs[i] @ (Q2[i * n:(i + 1) * n] * d)      # block of U, positive diag
+        Qs[i] = None
+        out[r0:r1] = Ui @ SVt
+        del Ui
+    return out
+
+
 def growth_blocks(m: int, n0: int, p: int, nblocks: int, kappa_lo: float,
                   kappa_hi: float, coupling: float = 1e-3, seed: int = 2):
     """Inputs of an iterative basis-growth run.

@@ -99,7 +99,7 @@ def test_orth_parity_20000x20_kappa1e6():
 
 
 @pytest.mark.parametrize("m,n", [(1000, 5), (4099, 16), (10007, 17), (5000, 33),
-                                 (3001, 64), (2000, 100)])
+                                 (3001, 64), (2000, 100), (2500, 128), (4097, 113)])
 @pytest.mark.parametrize("kappa", [1e2, 1e8, 1e12, 1e15])
 def test_orth_parity_sweep(m, n, kappa):
     A = S.test_matrix(m, n, kappa, seed=(3,))
