@@ -364,8 +364,10 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
   k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
   const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
-  k.lds_matrices = arena <= g_small_lds;
-  hipLaunchKernelGGL(small_step, dim3(1), dim3(kSmallThreads), k.lds_matrices ? arena : 0, s, k);
+  const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
+  k.lds_matrices = (arena <= g_small_lds) ? 1 : (mbytes <= g_small_lds ? 2 : 0);
+  const size_t dyn = k.lds_matrices == 1 ? arena : (k.lds_matrices == 2 ? mbytes : 0);
+  hipLaunchKernelGGL(small_step, dim3(1), dim3(kSmallThreads), dyn, s, k);
   return hipGetLastError() == hipSuccess ? SQR_OK : SQR_EHIP;
 }
 

@@ -79,7 +79,8 @@ struct SmallArgs {
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
   double tol, u;
-  int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X
+  int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X;
+                         // 2: only the factor M (p x p) lives in LDS
 };
 
 }  // namespace sqr

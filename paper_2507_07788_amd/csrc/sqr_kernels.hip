@@ -579,9 +579,10 @@ __device__ bool chol_upper(double* M, int p, bool lds_only) {
   for (int j = 0; j < p; ++j) {
     wg_sync(lds_only);
     const double d = M[(int64_t)j * p + j];
-    if (!(d > 0.0) || !isfinite(d)) return false;  // uniform: all read d
+    const bool bad = !(d > 0.0) || !isfinite(d);  // uniform: all read d
+    wg_sync(lds_only);  // every thread has read d before anyone returns or writes
+    if (bad) return false;
     const double r = sqrt(d);
-    wg_sync(lds_only);
     if (tid == 0) M[(int64_t)j * p + j] = r;
     for (int k = j + 1 + tid; k < p; k += kSmallThreads) M[(int64_t)j * p + k] /= r;
     wg_sync(lds_only);
@@ -664,7 +665,8 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   __shared__ int cflag;
   Ctrl* c = a.ctrl;
   const int tid = threadIdx.x;
-  const bool lo = a.lds_matrices != 0;   // matrices in LDS: LDS-only barriers
+  const bool lo = a.lds_matrices == 1;   // all matrices in LDS: LDS-only barriers
+  const bool mlo = a.lds_matrices != 0;  // the factor M in LDS
   int prev_att = 0;  // factorisations of earlier passes (thread 0)
   if (a.phase > 0) {
     if (c->done) return;
@@ -677,10 +679,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   }
   const int p = a.p, q = a.q;
   const int64_t pp = (int64_t)p * p, qp = (int64_t)q * p;
-  double* base = a.lds_matrices ? lds : a.X;   // arena (LDS, or workspace)
+  double* base = lo ? lds : a.X;   // arena (LDS, or workspace)
   double* X = base;
-  double* M = X + pp;
-  double* Ro = M + pp;          // old diagonal block of R (row-major)
+  double* M = (a.lds_matrices == 2) ? lds : X + pp;   // mode 2: only M in LDS
+  double* Ro = X + 2 * pp;      // old diagonal block of R (row-major)
   double* Bt = Ro + pp;         // B~ (row-major q x p)
   double* Bo = Bt + qp;         // B before this pass (append), q x p
   double* R = a.R;
@@ -797,11 +799,17 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   if (!shifted) {
     for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
     ++attempts;
-    ok = (p <= 64 && a.lds_matrices) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, lo);
+    ok = (p <= 64 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, mlo);
     shifted = !ok;
   }
   if (shifted) {
-    // ||X||_2 by power iteration from the all-ones vector.
+    // ||X||_2 by power iteration from the all-ones vector (on a copy of X in
+    // LDS when only M lives there: M is rebuilt from X below).
+    const double* Xs = X;
+    if (a.lds_matrices == 2) {
+      for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
+      Xs = M;
+    }
     for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
     wg_sync(lo);
     double lam = 0.0;
@@ -811,7 +819,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       for (int i = tid; i < p; i += kSmallThreads) {
         double t = 0.0;
 #pragma unroll 8
-        for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
+        for (int j = 0; j < p; ++j) t += Xs[(int64_t)i * p + j] * v[j];
         w[i] = t;
         pp2 += t * t;
       }
@@ -828,7 +836,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       double pp2 = 0.0;
       for (int i = tid; i < p; i += kSmallThreads) {
         double t = 0.0;
-        for (int j = 0; j < p; ++j) t += X[(int64_t)i * p + j] * v[j];
+        for (int j = 0; j < p; ++j) t += Xs[(int64_t)i * p + j] * v[j];
         pp2 += v[i] * t;
       }
       lam = fabs(block_sum(pp2, red, lo));
@@ -841,7 +849,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       for (int e = tid; e < pp; e += kSmallThreads)
         M[e] = X[e] + ((e / p == e % p) ? sigma : 0.0);
       ++attempts;
-      ok = (p <= 64 && a.lds_matrices) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, lo);
+      ok = (p <= 64 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, mlo);
       if (ok) break;
       if (esc >= a.max_escalations) break;
       sigma = fmax(10.0 * sigma, 2.0 * a.u);

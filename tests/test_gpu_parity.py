@@ -121,6 +121,22 @@ def test_orth_algorithm1_literal_fig1_shape(e):
     assert O.rrr(A, host(b.q()), host(b.r())) <= 1e-13
 
 
+@pytest.mark.parametrize("m,n", [(3000, 70), (2000, 100), (2100, 128)])
+def test_orth_breakdown_then_shift_wide(m, n):
+    """Algorithm 1 as printed: the unshifted first factorisation of a kappa =
+    1e15 Gramian breaks down and the shifted retry (power iteration, shift,
+    factorisation) runs on the wide-block paths."""
+    A = S.test_matrix(m, n, 1e15, seed=(9,))
+    kw = dict(first_pass_shift=0, min_passes=0)
+    Qo, Ro, io = O.orth(A, **kw)
+    assert io["chol_attempts"] > io["passes"]          # the oracle broke down
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0
+    assert info["chol_attempts"] > info["passes"]
+    assert abs(info["passes"] - io["passes"]) <= 1
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e15)
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 5), (16, 16), (17, 3), (33, 20), (31, 31)])
 def test_orth_tiny_and_square(m, n):
     A = S.test_matrix(m, n, 10.0, seed=(4,))
