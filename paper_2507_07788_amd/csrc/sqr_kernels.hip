@@ -586,10 +586,11 @@ __device__ bool chol_upper(double* M, int p, bool lds_only) {
     if (tid == 0) M[(int64_t)j * p + j] = r;
     for (int k = j + 1 + tid; k < p; k += kSmallThreads) M[(int64_t)j * p + k] /= r;
     wg_sync(lds_only);
-    const int w = p - j - 1;
-    for (int e = tid; e < w * w; e += kSmallThreads) {
-      const int i = j + 1 + e / w, k = j + 1 + e % w;
-      if (k >= i) M[(int64_t)i * p + k] -= M[(int64_t)j * p + i] * M[(int64_t)j * p + k];
+    // trailing update of the upper part: rows dealt to 16 thread groups,
+    // columns to the 16 threads of a group
+    for (int i = j + 1 + (tid >> 4); i < p; i += kSmallThreads / 16) {
+      const double mji = M[(int64_t)j * p + i];
+      for (int k = i + (tid & 15); k < p; k += 16) M[(int64_t)i * p + k] -= mji * M[(int64_t)j * p + k];
     }
   }
   wg_sync(lds_only);
@@ -621,6 +622,98 @@ __device__ bool chol_upper_wave(double* M, int p, int* flag) {
   }
   wg_sync(true);
   return *flag != 0;
+}
+
+// dst[i * cols + j] = f(i, j) over a rows x cols row-major matrix.  Each
+// row is padded to whole 16-column chunks; the padded index space is dealt
+// to the threads in batches of eight whose values are all loaded before any
+// is stored (dst may alias the sources as far as the compiler knows, which
+// would otherwise put every load behind the previous store).
+template <class F>
+__device__ __forceinline__ void fill_rows(double* dst, int rows, int cols, F f) {
+  if (rows * cols <= kSmallThreads * 8) {   // small: one element per thread and step
+    for (int e = threadIdx.x; e < rows * cols; e += kSmallThreads) {
+      const int i = e / cols;
+      dst[e] = f(i, e - i * cols);
+    }
+    return;
+  }
+  const int width = (cols + 15) & ~15;
+  const int total = rows * width;
+  for (int b = threadIdx.x; b < total; b += kSmallThreads * 8) {
+    double t[8];
+    int ii[8], jj[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b + kSmallThreads * u;
+      ii[u] = idx / width;
+      jj[u] = idx - ii[u] * width;
+      t[u] = (idx < total && jj[u] < cols) ? f(ii[u], jj[u]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b + kSmallThreads * u;
+      if (idx < total && jj[u] < cols) dst[(int64_t)ii[u] * cols + jj[u]] = t[u];
+    }
+  }
+}
+
+// Blocked right-looking form of the same factorisation for p > 16: the 16
+// rows of band K are factored column by column (the band's rows against all
+// columns to their right), then every trailing block (I, J), K < I <= J, is
+// updated as M_IJ -= R_KI^T R_KJ on MFMA.  Breakdown is decided on the
+// pivot as it stands after all earlier updates, as in the unblocked form.
+__device__ bool chol_blocked(double* M, int p, bool lds_only) {
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, ln = tid & 63, x = ln & 15, g = ln >> 4;
+  const int nbk = (p + 15) >> 4;
+  for (int K = 0; K < nbk; ++K) {
+    const int b0 = 16 * K, b1 = min(p, b0 + 16);
+    for (int j = b0; j < b1; ++j) {
+      wg_sync(lds_only);
+      const double d = M[(int64_t)j * p + j];
+      if (!(d > 0.0) || !isfinite(d)) {   // uniform: all read d
+        wg_sync(lds_only);                // before the caller rewrites M
+        return false;
+      }
+      const double r = sqrt(d);
+      for (int c = j + 1 + tid; c < p; c += kSmallThreads) M[(int64_t)j * p + c] /= r;
+      wg_sync(lds_only);
+      if (tid == 0) M[(int64_t)j * p + j] = r;
+      for (int i = j + 1 + (tid >> 4); i < b1; i += kSmallThreads / 16) {
+        const double mji = M[(int64_t)j * p + i];
+        for (int c = i + (tid & 15); c < p; c += 16) M[(int64_t)i * p + c] -= mji * M[(int64_t)j * p + c];
+      }
+    }
+    wg_sync(lds_only);
+    const int rem = nbk - K - 1;
+    for (int t = wv; t < rem * (rem + 1) / 2; t += kSmallWaves) {
+      int Jr = 0;
+      while ((Jr + 1) * (Jr + 2) / 2 <= t) ++Jr;
+      const int I = K + 1 + (t - Jr * (Jr + 1) / 2), J = K + 1 + Jr;
+      const int ci = 16 * I + x, cj = 16 * J + x;
+      d4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + g + 4 * r;
+        acc[r] = (row < p && cj < p) ? M[(int64_t)row * p + cj] : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kk = b0 + 4 * s4 + g;
+        const double av = (kk < b1 && ci < p) ? -M[(int64_t)kk * p + ci] : 0.0;
+        const double bv = (kk < b1 && cj < p) ? M[(int64_t)kk * p + cj] : 0.0;
+        acc = mfma(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + g + 4 * r;
+        if (row < p && cj < p) M[(int64_t)row * p + cj] = acc[r];
+      }
+    }
+  }
+  wg_sync(lds_only);
+  return true;
 }
 
 // Doubles small_step keeps in LDS when they fit: X, M, R_old (p x p each),
@@ -660,8 +753,12 @@ __device__ void publish(const SmallArgs& a, const Outcome& o) {
 __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[kSmallWaves];
-  __shared__ double v[kMaxCols], w[kMaxCols];
-  __shared__ double dls[4 * 256];    // inverted diagonal blocks (p <= 64)
+  // power-iteration vectors, Schur partial sums, then (up to 8 blocks) the
+  // inverted diagonal blocks D_J for forming C_J
+  __shared__ double vw[2 * kMaxCols];
+  double* v = vw;
+  double* w = vw + kMaxCols;
+  constexpr int kLdsDBlocks = 2 * kMaxCols / 256;
   __shared__ int cflag;
   Ctrl* c = a.ctrl;
   const int tid = threadIdx.x;
@@ -705,27 +802,22 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
   //    G = E[q:q+p, :] (upper, mirrored).
   const int q4 = (q + 3) & ~3;
-  for (int e = tid; e < p * p; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
+  const double* E = a.E;
+  fill_rows(X, p, p, [&](int i, int j) {
     const int lo = min(i, j), hi = max(i, j);
-    X[e] = a.E[e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
-  }
-  for (int e = tid; e < qp; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
-    Bt[e] = a.E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
-  }
+    return E[e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
+  });
+  fill_rows(Bt, q, p, [&](int i, int j) {
+    return E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
+  });
   // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2) and
   // old B (zero at phase 0), loaded together with the Gramian blocks
-  for (int e = tid; e < pp; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
-    Ro[e] = (a.phase == 0) ? (i == j ? 1.0 : 0.0) : R[roff + i + (int64_t)j * ldr];
-  }
-  if (a.mode == 1) {
-    for (int e = tid; e < qp; e += kSmallThreads) {
-      const int i = e / p, j = e % p;
-      Bo[e] = (a.phase == 0) ? 0.0 : R[i + (int64_t)(q + j) * ldr];
-    }
-  }
+  const bool ph0 = a.phase == 0;
+  fill_rows(Ro, p, p, [&](int i, int j) {
+    return ph0 ? (i == j ? 1.0 : 0.0) : R[roff + i + (int64_t)j * ldr];
+  });
+  if (a.mode == 1)
+    fill_rows(Bo, q, p, [&](int i, int j) { return ph0 ? 0.0 : R[i + (int64_t)(q + j) * ldr]; });
   // phase 0: the stores of R above precede the stores of step 6 by other threads
   wg_sync(lo && a.phase > 0);
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
@@ -765,10 +857,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   }
   // 3. ||X - I||_F.
   double part = 0.0;
-  for (int e = tid; e < pp; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
-    const double d = X[e] - (i == j ? 1.0 : 0.0);
-    part += d * d;
+  for (int i = tid >> 4; i < p; i += kSmallThreads / 16) {
+#pragma unroll 4
+    for (int j = tid & 15; j < p; j += 16) {
+      const double d = X[(int64_t)i * p + j] - (i == j ? 1.0 : 0.0);
+      part += d * d;
+    }
   }
   const double err = sqrt(block_sum(part, red, lo));
   // 4. Stopping test (Algorithm 1 with the CholQR3 start; Algorithm 2).
@@ -797,9 +891,9 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   double sigma = 0.0;
   bool ok = false;
   if (!shifted) {
-    for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
+    fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
     ++attempts;
-    ok = (p <= 64 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, mlo);
+    ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_blocked(M, p, mlo);
     shifted = !ok;
   }
   if (shifted) {
@@ -807,7 +901,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     // LDS when only M lives there: M is rebuilt from X below).
     const double* Xs = X;
     if (a.lds_matrices == 2) {
-      for (int e = tid; e < pp; e += kSmallThreads) M[e] = X[e];
+      fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
       Xs = M;
     }
     for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
@@ -846,10 +940,9 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
                                      : (mm * q + (double)q * (q + 1));
     sigma = fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
     for (int esc = 0;; ++esc) {
-      for (int e = tid; e < pp; e += kSmallThreads)
-        M[e] = X[e] + ((e / p == e % p) ? sigma : 0.0);
+      fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
       ++attempts;
-      ok = (p <= 64 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_upper(M, p, mlo);
+      ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_blocked(M, p, mlo);
       if (ok) break;
       if (esc >= a.max_escalations) break;
       sigma = fmax(10.0 * sigma, 2.0 * a.u);
@@ -895,18 +988,50 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       }
     }
   }
-  for (int e = tid; e < pp; e += kSmallThreads) {
-    const int i = e / p, j = e % p;
-    double s = 0.0;
-    if (p <= 16) {
+  if (p <= 16) {
+    for (int e = tid; e < pp; e += kSmallThreads) {
+      const int i = e / p, j = e % p;
+      double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k)
         if (k >= i && k <= j) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
-    } else {
-#pragma unroll 4
-      for (int k = i; k <= j; ++k) s += M[(int64_t)i * p + k] * Ro[(int64_t)k * p + j];
+      R[roff + i + (int64_t)j * ldr] = (i <= j) ? s : 0.0;
     }
-    R[roff + i + (int64_t)j * ldr] = (i <= j) ? s : 0.0;
+  } else {
+    // 16x16 tiles (I <= J) of the product of two upper triangular matrices
+    // on MFMA, one tile per wave at a time: the wave forms the transposed
+    // tile, sum_K Ro_KJ^T M_IK^T, with the strictly lower part of M (which
+    // holds no factor entries) masked to zero.
+    const int wv = tid >> 6, ln = tid & 63, x = ln & 15, g = ln >> 4;
+    const int nbk = (p + 15) >> 4;
+    for (int t = wv; t < nbk * (nbk + 1) / 2; t += kSmallWaves) {
+      int J = 0;
+      while ((J + 1) * (J + 2) / 2 <= t) ++J;
+      const int I = t - J * (J + 1) / 2;
+      const int ii = 16 * I + x, jj = 16 * J + x;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      for (int K0 = I; K0 <= J; K0 += 4) {   // operands of four K blocks in flight
+        double av[16], bv[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int kk = 16 * K0 + 4 * e + g;   // e = 4 (K - K0) + s4
+          const bool in = K0 + (e >> 2) <= J && kk < p;
+          av[e] = (in && jj < p && kk <= jj) ? Ro[(int64_t)kk * p + jj] : 0.0;
+          bv[e] = (in && ii < p && kk >= ii) ? M[(int64_t)ii * p + kk] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc = mfma(av[e], bv[e], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * J + g + 4 * r;
+        if (ii < p && j < p) R[roff + ii + (int64_t)j * ldr] = (ii <= j) ? acc[r] : 0.0;
+      }
+    }
+    for (int e = tid; e < pp; e += kSmallThreads) {   // tiles below the diagonal
+      const int i = e % p, j = e / p;
+      if ((i >> 4) > (j >> 4)) R[roff + i + (int64_t)j * ldr] = 0.0;
+    }
   }
   // 7. Operands of the next pass.  D_J = inverse of the diagonal block J of
   //    R~ (identity beyond p), by back substitution on each column.
@@ -936,12 +1061,13 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     double* rv = a.rinv + J * 256;
 #pragma unroll
     for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
-    if (a.nblk <= 4) {
+    if (a.nblk <= kLdsDBlocks) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) dls[J * 256 + i * 16 + cc] = col[i];
+      for (int i = 0; i < 16; ++i) vw[J * 256 + i * 16 + cc] = col[i];
     }
   }
-  wg_sync(lo && a.nblk <= 4);  // D_J complete (LDS, or global beyond 4 blocks)
+  // D_J complete (in LDS, or in global memory beyond kLdsDBlocks blocks)
+  wg_sync(a.nblk <= kLdsDBlocks);
   //    C_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]] D_J, so the
   //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
   //    One row of C_J per thread: the row of the source in registers, D_J
@@ -949,7 +1075,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
     const int rows = q4 + b0;
-    const double* D = (a.nblk <= 4) ? dls + J * 256 : a.rinv + J * 256;
+    const double* D = (a.nblk <= kLdsDBlocks) ? vw + J * 256 : a.rinv + J * 256;
     double* bn = a.bneg + 16 * ((int64_t)J * q4 + 8 * (int64_t)J * (J - 1));
     for (int kk = tid; kk < rows; kk += kSmallThreads) {
       double src[16];
