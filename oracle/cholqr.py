@@ -23,6 +23,14 @@ Readings of the paper taken here (each one is also listed in the design notes):
     (LAPACK potrf semantics).
   * Columns are never dropped on a lucky breakdown (Sec. 2.2): such a call ends
     as "not converged".
+
+The mixed-precision form of ``orth`` (``precision=1``) is not in the paper;
+it follows this build's reading: Gramians of the shifted passes and of the
+first unshifted pass are formed from the FP32-rounded iterate with FP32
+accumulation, everything else (applies, shift estimate, Cholesky, the Gramian
+that feeds the final pass and the stopping test) stays FP64.  An FP32 Gramian
+never satisfies the stopping test; its shift is n * u32 * ||X|| (u32 = 2^-24,
+floor 2 u32), escalated x10 on breakdown like Algorithm 2's.
 """
 from __future__ import annotations
 
@@ -32,6 +40,8 @@ import numpy as np
 
 #: unit roundoff of IEEE FP64 (Sec. 3.1)
 U64 = 2.0 ** -53
+#: unit roundoff of IEEE FP32 (mixed form only)
+U32 = 2.0 ** -24
 
 OK = 0
 NOT_CONVERGED = 1
@@ -46,6 +56,20 @@ def gram(Q: np.ndarray) -> np.ndarray:
     """X = Q^T Q (Algorithm 1, Gram steps).  Upper triangle, mirrored."""
     X = Q.T @ Q
     return np.triu(X) + np.triu(X, 1).T
+
+
+def gram_fp32(Q: np.ndarray) -> np.ndarray:
+    """Q^T Q of the FP32-rounded Q with FP32 accumulation, returned in FP64
+    (mixed form)."""
+    Q32 = np.asarray(Q, dtype=np.float64).astype(np.float32)
+    G = Q32.T @ Q32
+    G = np.triu(G) + np.triu(G, 1).T
+    return G.astype(np.float64)
+
+
+def shift_fp32(n: int, xnorm: float) -> float:
+    """Shift of a pass driven by an FP32 Gramian: max(n u32 ||X||, 2 u32)."""
+    return max(n * U32 * xnorm, 2.0 * U32)
 
 
 def gram_append(Q_in: np.ndarray, W: np.ndarray):
@@ -151,7 +175,7 @@ def default_opts(**kw) -> dict:
     """Options of the drivers; defaults give CholQR3 (a shifted first pass,
     then CholeskyQR2, then Algorithm 1's continuation)."""
     opts = dict(first_pass_shift=1, min_passes=3, max_iter=10, tol=1e-13,
-                unit_roundoff=U64, max_escalations=32, power_steps=30)
+                unit_roundoff=U64, max_escalations=32, power_steps=30, precision=0)
     opts.update(kw)
     return opts
 
@@ -174,8 +198,10 @@ def orth(A: np.ndarray, **kw):
     m, n = A.shape
     Q = A.copy()
     R = np.eye(n)
-    X = gram(Q)
-    info = dict(status=OK, passes=0, sigma=[], chol_attempts=0, orth_fro=None)
+    g32 = int(o["precision"]) == 1      # the Gramian at hand is an FP32 one
+    X = gram_fp32(Q) if g32 else gram(Q)
+    info = dict(status=OK, passes=0, sigma=[], chol_attempts=0, orth_fro=None,
+                fp32_grams=int(g32))
     passes = 0
     while True:
         err = fro_dist_identity(X)
@@ -183,7 +209,7 @@ def orth(A: np.ndarray, **kw):
         if not math.isfinite(err):
             info["status"] = ENONFINITE
             break
-        if passes >= o["min_passes"] and err < o["tol"]:
+        if not g32 and passes >= o["min_passes"] and err < o["tol"]:
             break
         if passes >= o["max_iter"]:
             info["status"] = NOT_CONVERGED
@@ -197,9 +223,12 @@ def orth(A: np.ndarray, **kw):
             shifted = not ok
         if shifted:
             lam = lambda_max(X, o["power_steps"])
-            sigma0 = shift_orth(m, n, lam, u)
-            Rt, sigma, att, ok = _chol_with_escalation(X, sigma0, u,
-                                                       o["max_escalations"])
+            if g32:
+                Rt, sigma, att, ok = _chol_with_escalation(X, shift_fp32(n, lam), U32,
+                                                           o["max_escalations"])
+            else:
+                Rt, sigma, att, ok = _chol_with_escalation(X, shift_orth(m, n, lam, u), u,
+                                                           o["max_escalations"])
             info["chol_attempts"] += att
             if not ok:
                 info["status"] = BREAKDOWN
@@ -207,7 +236,9 @@ def orth(A: np.ndarray, **kw):
         info["sigma"].append(sigma)
         Q = apply_inverse(Q, Rt)
         R = Rt @ R
-        X = gram(Q)
+        g32 = g32 and shifted           # FP32 Gramians end after an unshifted pass
+        info["fp32_grams"] += int(g32)
+        X = gram_fp32(Q) if g32 else gram(Q)
     info["passes"] = passes
     return Q, R, info
 

@@ -430,3 +430,75 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with monkeypatch.context() as mp:
         mp.setattr(C.math, "sqrt", lambda x: x)
         assert _fails(append_pin)
+
+
+# ---------------------------------------------------------------------------
+# mixed-precision form (precision=1): FP32 Gramians until the first unshifted
+# pass, then FP64 (a reading of this build; the paper has no mixed form)
+# ---------------------------------------------------------------------------
+def test_shift_fp32_exact():
+    assert O.shift_fp32(16, 1.0) == 16 * 2.0 ** -24
+    assert O.shift_fp32(256, 0.5) == 128 * 2.0 ** -24
+    assert O.shift_fp32(16, 0.0) == 2.0 ** -23          # floor 2 u32
+
+
+def test_gram_fp32_rounds_the_iterate():
+    # integer entries: FP32 rounding and accumulation are exact
+    A = np.array([[1.0, 2.0], [3.0, -4.0], [5.0, 6.0]])
+    assert np.array_equal(O.gram_fp32(A), A.T @ A)
+    # 1 + 2^-30 is not an FP32 number: the FP32 Gramian sees 1
+    B = np.array([[1.0 + 2.0 ** -30], [0.0]])
+    assert O.gram_fp32(B)[0, 0] == 1.0
+    assert O.gram(B)[0, 0] > 1.0
+
+
+def test_mixed_orthonormal_input_needs_fp64_pass():
+    # FP64 sees an orthonormal input and stops at once; an FP32 Gramian can
+    # never stop the iteration, so the mixed form makes an unshifted pass on
+    # it (an R~ accurate to FP32 only), one FP64 pass, and stops on the FP64
+    # check Gramian.
+    Q0 = S.orthonormal(S.rng(11), 5000, 12)
+    _, _, i64 = O.orth(Q0, first_pass_shift=0, min_passes=0)
+    assert i64["passes"] == 0
+    _, _, im = O.orth(Q0, first_pass_shift=0, min_passes=0, precision=1)
+    assert im["status"] == O.OK
+    assert im["passes"] == 2 and im["fp32_grams"] == 1
+    assert im["sigma"] == [0.0, 0.0]
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
+def test_mixed_orth_is_the_qr(kappa):
+    A = S.test_matrix(6000, 16, kappa, seed=(12,))
+    Q, R, i64 = O.orth(A)
+    Qm, Rm, im = O.orth(A, precision=1)
+    assert im["status"] == O.OK
+    assert O.loo(Qm) <= 1e-13 and O.rrr(A, Qm, Rm) <= 1e-14
+    assert np.abs(Rm - R).max() <= 1e-10 * kappa * np.abs(R).max()
+    # FP32 Gramians for every shifted pass and the first unshifted one, then
+    # exactly one FP64 pass and the FP64 check
+    assert im["fp32_grams"] == im["passes"] - 1
+    assert im["passes"] >= i64["passes"]
+    assert all(s > 0 for s in im["sigma"][:im["passes"] - 2])
+    assert im["sigma"][im["passes"] - 1] == 0.0
+    # ||A||_2 = 1 by construction, so the first FP32 shift is 16 u32 (to the
+    # accuracy of the norm estimate) and no shifted factorisation escalates
+    assert abs(im["sigma"][0] / (16 * 2.0 ** -24) - 1.0) < 1e-2
+    nshift = sum(s > 0 for s in im["sigma"])
+    assert im["chol_attempts"] == im["passes"] + nshift - 1
+
+
+def test_planted_mixed_mistakes_are_caught(monkeypatch):
+    import oracle.cholqr as C
+    pin = test_mixed_orthonormal_input_needs_fp64_pass
+    qr_pin = lambda: test_mixed_orth_is_the_qr(1e8)
+    assert not _fails(pin) and not _fails(qr_pin)
+    mistakes = [
+        # FP64 Gramians throughout (the FP32 rounding left out)
+        ("gram_fp32", C.gram, pin),
+        # FP64 shift constant in the FP32 passes (shift far too small)
+        ("shift_fp32", lambda n, x: max(n * C.U64 * x, 2 * C.U64), qr_pin),
+    ]
+    for name, bad, p in mistakes:
+        with monkeypatch.context() as mp:
+            mp.setattr(C, name, bad)
+            assert _fails(p), name
