@@ -39,7 +39,15 @@ extern "C" {
 /* Options.  Defaults (sqr_default_opts) are the paper's experimental settings
  * (Sec. 3.1: tolerance 1e-13 on ||I - Q^T Q||_F, at most 10 iterations). */
 typedef struct sqr_opts {
-  int32_t precision;        /* 0 = FP64 throughout (the only value accepted)    */
+  int32_t precision;        /* 0 = FP64 throughout.  1 = mixed form of sqr_orth
+                               (n <= 128): the Gramians of the shifted passes
+                               and of the first unshifted pass are formed on
+                               FP32 MFMA from the FP32-rounded iterate; applies,
+                               shift estimates, Cholesky and the Gramians of the
+                               final pass and of the check stay FP64.  An FP32
+                               Gramian never ends the iteration; its shift is
+                               n u32 ||X||_2 (u32 = 2^-24, floor 2 u32), x10 on
+                               breakdown.  sqr_append always runs in FP64.     */
   int32_t first_pass_shift; /* 1 = CholQR3 start (shifted pass 1); 0 = Alg. 1   */
   int32_t min_passes;       /* passes run before the stopping test is consulted;
                                3 for CholQR3, 0 for Algorithm 1 as printed      */
@@ -89,7 +97,8 @@ void sqr_default_opts(sqr_opts* o);
  * Ownership: A, Q and R are borrowed and must stay allocated until the work
  * enqueued on `stream` completes.  The handle owns only its workspace.
  * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
- * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT, SQR_EHIP; all
+ * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT (also for
+ * precision 1 with n > 128), SQR_EHIP; all
  * before any work is enqueued, except SQR_EHIP from a failed launch.
  */
 int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,

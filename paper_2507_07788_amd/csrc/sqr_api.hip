@@ -114,15 +114,17 @@ const Variant kVariants[] = {
 };
 #undef SQR_VARIANT
 
-// Whole-pass kernels of orth calls with 2..8 column blocks.
+// Whole-pass kernels of orth calls with up to 8 column blocks (FP64 calls use
+// them from 2 blocks on; the mixed form from 1), with FP64 or FP32 Gramians.
 typedef void (*WideKernel)(WidePassArgs);
-struct WideVariant { WideKernel gram, apply; };
-#define SQR_WIDE(NB) {wide_pass<NB, false>, wide_pass<NB, true>}
-constexpr int kWideMin = 2, kWideMax = 8;
-const WideVariant kWide[] = {SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4), SQR_WIDE(5),
-                             SQR_WIDE(6), SQR_WIDE(7), SQR_WIDE(8)};
+struct WideVariant { WideKernel k[2][2]; };   // [fp32 gram][apply]
+#define SQR_WIDE(NB) {{{wide_pass<NB, false, false>, wide_pass<NB, true, false>}, \
+                       {wide_pass<NB, false, true>, wide_pass<NB, true, true>}}}
+constexpr int kWideMin = 1, kWideMax = 8;
+const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
+                             SQR_WIDE(5), SQR_WIDE(6), SQR_WIDE(7), SQR_WIDE(8)};
 #undef SQR_WIDE
-int g_wide_occ[2][kWideMax - kWideMin + 1];
+int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 size_t wide_lds_bytes(int nb, bool apply) {
   return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));
 }
@@ -153,11 +155,11 @@ void set_kernel_attributes() {
     g_small_lds = 0;
   }
   for (int nb = kWideMin; nb <= kWideMax; ++nb)
-    for (int ap = 0; ap < 2; ++ap) {
-      const WideKernel k = ap ? kWide[nb - kWideMin].apply : kWide[nb - kWideMin].gram;
-      (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)wide_lds_bytes(nb, ap != 0));
-    }
+    for (int g32 = 0; g32 < 2; ++g32)
+      for (int ap = 0; ap < 2; ++ap)
+        (void)hipFuncSetAttribute((const void*)kWide[nb - kWideMin].k[g32][ap],
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)wide_lds_bytes(nb, ap != 0));
   (void)hipGetLastError();
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -177,15 +179,16 @@ void set_kernel_attributes() {
     ++i;
   }
   for (int nb = kWideMin; nb <= kWideMax; ++nb)
-    for (int ap = 0; ap < 2; ++ap) {
-      const WideKernel k = ap ? kWide[nb - kWideMin].apply : kWide[nb - kWideMin].gram;
-      int n = 1;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k, kThreads,
-                                                        wide_lds_bytes(nb, ap != 0)) != hipSuccess ||
-          n < 1)
-        n = 1;
-      g_wide_occ[ap][nb - kWideMin] = n;
-    }
+    for (int g32 = 0; g32 < 2; ++g32)
+      for (int ap = 0; ap < 2; ++ap) {
+        int n = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, (const void*)kWide[nb - kWideMin].k[g32][ap], kThreads,
+                wide_lds_bytes(nb, ap != 0)) != hipSuccess ||
+            n < 1)
+          n = 1;
+        g_wide_occ[g32][ap][nb - kWideMin] = n;
+      }
   g_attr_done = true;
 }
 
@@ -262,11 +265,15 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   const int64_t tiles = (b->m + 15) / 16;
   const bool apply = phase > 0;
   int64_t nwg = b->slots;
-  if (c.mode == 0 && P >= kWideMin && P <= kWideMax) {
-    // the whole pass in one launch
+  const bool mixed = c.mode == 0 && b->opts.precision == 1;
+  if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
+    // the whole pass in one launch (mixed form: one launch per Gramian
+    // precision from pass 1 on; the one that does not match the device's
+    // choice exits at once)
     const int idx = (int)P - kWideMin;
     const int64_t steps = (tiles + kWaves - 1) / kWaves;
-    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_wide_occ[apply ? 1 : 0][idx]);
+    const int occ = std::min(g_wide_occ[0][apply ? 1 : 0][idx], g_wide_occ[1][apply ? 1 : 0][idx]);
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
     nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, steps));
     WidePassArgs w;
     memset(&w, 0, sizeof(w));
@@ -288,10 +295,16 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       rec.call = b->call_id; rec.phase = phase; rec.real = -1;
       if (rec.e0) (void)hipEventRecord(rec.e0, s);
     }
-    const WideKernel k = apply ? kWide[idx].apply : kWide[idx].gram;
-    if (hipLaunchKernel((const void*)k, dim3((unsigned)nwg), dim3(kThreads), args,
-                        wide_lds_bytes((int)P, apply), s) != hipSuccess)
-      return SQR_EHIP;
+    for (int g32 = mixed ? 1 : 0; g32 >= 0; --g32) {
+      // phase 0 of the mixed form is an FP32 Gramian; later phases follow the
+      // device (ctrl->gram32); FP64 calls launch the FP64 variant only
+      if (mixed && phase == 0 && g32 == 0) break;
+      w.gram32 = (mixed && phase > 0) ? &b->ctrl->gram32 : nullptr;
+      const WideKernel k = kWide[idx].k[g32][apply ? 1 : 0];
+      if (hipLaunchKernel((const void*)k, dim3((unsigned)nwg), dim3(kThreads), args,
+                          wide_lds_bytes((int)P, apply), s) != hipSuccess)
+        return SQR_EHIP;
+    }
     if (g_prof_on && rec.e0 && rec.e1) {
       (void)hipEventRecord(rec.e1, s);
       g_prof.push_back(rec);
@@ -363,6 +376,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
   k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
   k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+  k.mixed = mixed ? 1 : 0;
   const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
   const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
   k.lds_matrices = (arena <= g_small_lds) ? 1 : (mbytes <= g_small_lds ? 2 : 0);
@@ -437,7 +451,7 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
 }
 
 bool opts_ok(const sqr_opts& o) {
-  return o.precision == 0 && o.max_iter >= 1 && o.max_iter <= 64 && o.min_passes >= 0 &&
+  return (o.precision == 0 || o.precision == 1) && o.max_iter >= 1 && o.max_iter <= 64 && o.min_passes >= 0 &&
          o.tol > 0.0 && o.unit_roundoff > 0.0 && o.max_escalations >= 0 &&
          o.power_steps >= 1 && o.power_steps <= 1000;
 }
@@ -469,6 +483,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   sqr_default_opts(&o);
   if (opts) o = *opts;
   if (!opts_ok(o)) return SQR_EOPT;
+  if (o.precision == 1 && n > 16 * kWideMax) return SQR_EOPT;   // mixed form up to 128 columns
   set_kernel_attributes();
   sqr_basis* b = new sqr_basis();
   b->m = m; b->n = n; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;

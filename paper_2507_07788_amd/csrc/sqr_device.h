@@ -19,7 +19,8 @@ struct Ctrl {
   int32_t passes;         // Cholesky QR passes executed so far
   int32_t chol_attempts;  // factorisations tried, failed ones included
   int32_t converged;
-  int32_t pad[3];
+  int32_t gram32;         // mixed form: the next pass forms an FP32 Gramian
+  int32_t pad[2];
   double orth_fro;        // last ||X - I||_F
   double sigma[16];       // shift of each pass (0 = unshifted)
   int64_t stamp;          // host copy only: call id * 256 + phase of the last
@@ -54,6 +55,9 @@ struct WidePassArgs {
   const int32_t* done;                // NULL in the initial Gram pass of a call
   const int32_t* passes;
   int32_t copy_if_done;
+  // mixed form: the launch runs only if *gram32 equals the variant's Gramian
+  // precision (1 = FP32); NULL: it always runs
+  const int32_t* gram32;
 };
 
 // One launch of small_step: finish a pass of an orth or append call.
@@ -79,6 +83,7 @@ struct SmallArgs {
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
   double tol, u;
+  int32_t mixed;         // orth in the mixed FP32/FP64 form
   int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X;
                          // 2: only the factor M (p x p) lives in LDS
 };

@@ -32,11 +32,18 @@
 namespace sqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   // D = A (16x4) * B (4x16) + C.  Lane l supplies A[l%16][l/16] and
   // B[l/16][l%16]; it holds D[l/16 + 4r][l%16] in register r.
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  // FP32 counterpart (same operand lanes); lane l holds D[4 (l/16) + r][l%16]
+  // in register r.
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // Wave-private LDS hand-off: every lane's earlier LDS writes are complete and
@@ -383,7 +390,7 @@ __host__ __device__ constexpr int wide_panel_doubles(int nb) { return 128 * nb *
 constexpr int kOpSlot = 68;   // one 4 x 16 operand slot, rows padded to 17
 __host__ __device__ constexpr int wide_op_doubles(int nb) { return kWaves * nb * 4 * kOpSlot; }
 
-template <int NB, bool APPLY>
+template <int NB, bool APPLY, bool G32>
 __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
   extern __shared__ double lds[];
   constexpr int NP = NB * (NB + 1) / 2;           // Gramian blocks (I <= J)
@@ -397,6 +404,7 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
   const int64_t s0 = (int64_t)blockIdx.x * per;
   const int64_t s1 = min(steps, s0 + per);
 
+  if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
   if (a.done && *a.done) {
     if (APPLY && a.copy_if_done && *a.passes == 0) {
       for (int64_t t = s0 * kWaves + wave; t < min(tiles, s1 * kWaves); t += kWaves) {
@@ -442,12 +450,16 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
       }
   };
 
-  d4 acc[KP];
+  d4 acc[G32 ? 1 : KP];
+  f4 acc32[G32 ? KP : 1];
   int pi[KP], pj[KP];   // owned Gramian blocks (I, J), I <= J
   bool pidx_ok[KP];
 #pragma unroll
+  for (int k = 0; k < (G32 ? 1 : KP); ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < (G32 ? KP : 1); ++k) acc32[k] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
   for (int k = 0; k < KP; ++k) {
-    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
     const int pidx = wave + kWaves * k;
     pidx_ok[k] = pidx < NP;
     int J = 0;
@@ -504,25 +516,51 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
     // Operand order for the Gramian: slot (J, u) holds Y[row 4u + g'][16 J + c]
     // of this wave's tile at g' * 17 + c (padded rows: the transposing
     // stores and the operand loads both spread over the LDS banks).
+    if (G32) {
+      // mixed form: the Gramian of the FP32-rounded tile, FP32 accumulation
+      float* myop32 = reinterpret_cast<float*>(myop);
 #pragma unroll
-    for (int J = 0; J < NB; ++J)
+      for (int J = 0; J < NB; ++J)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = y[J][r];
-    __syncthreads();
+        for (int r = 0; r < 4; ++r)
+          myop32[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = (float)y[J][r];
+      __syncthreads();
+      const float* op32 = reinterpret_cast<const float*>(op);
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      if (pidx_ok[k]) {
-        const double* oa = op + pi[k] * 4 * kOpSlot + x + 17 * g;
-        const double* ob = op + pj[k] * 4 * kOpSlot + x + 17 * g;
+      for (int k = 0; k < KP; ++k) {
+        if (pidx_ok[k]) {
+          const float* oa = op32 + pi[k] * 4 * kOpSlot + x + 17 * g;
+          const float* ob = op32 + pj[k] * 4 * kOpSlot + x + 17 * g;
 #pragma unroll
-        for (int t = 0; t < kWaves; ++t)
+          for (int t = 0; t < kWaves; ++t)
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+            for (int u = 0; u < 4; ++u)
+              acc32[k] = mfma32(oa[(2 * t * NB * 4 + u) * kOpSlot], ob[(2 * t * NB * 4 + u) * kOpSlot],
+                                acc32[k]);
+        }
       }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = y[J][r];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        if (pidx_ok[k]) {
+          const double* oa = op + pi[k] * 4 * kOpSlot + x + 17 * g;
+          const double* ob = op + pj[k] * 4 * kOpSlot + x + 17 * g;
+#pragma unroll
+          for (int t = 0; t < kWaves; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // Slot: block J holds rows 0..16J+15 of Gramian columns 16J..16J+15.
@@ -531,8 +569,12 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
   for (int k = 0; k < KP; ++k) {
     if (pidx_ok[k]) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+      for (int r = 0; r < 4; ++r) {
+        if (G32)
+          out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + 4 * g + r) * 16 + x] = (double)acc32[k][r];
+        else
+          out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+      }
     }
   }
 }
@@ -765,13 +807,15 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   const bool lo = a.lds_matrices == 1;   // all matrices in LDS: LDS-only barriers
   const bool mlo = a.lds_matrices != 0;  // the factor M in LDS
   int prev_att = 0;  // factorisations of earlier passes (thread 0)
+  // mixed form: is the Gramian of this pass an FP32 one?
+  const bool cur32 = (a.phase == 0) ? (a.mixed != 0) : (a.mixed != 0 && c->gram32 != 0);
   if (a.phase > 0) {
     if (c->done) return;
     if (tid == 0) prev_att = c->chol_attempts;
   } else if (tid == 0) {
     // first small_step of a call: fresh state
     c->done = 0; c->status = 0; c->passes = 0; c->chol_attempts = 0;
-    c->converged = 0; c->orth_fro = 0.0;
+    c->converged = 0; c->orth_fro = 0.0; c->gram32 = a.mixed;
     for (int i = 0; i < 16; ++i) c->sigma[i] = 0.0;
   }
   const int p = a.p, q = a.q;
@@ -869,7 +913,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   int status = -1;
   if (!isfinite(err)) {
     status = 3;  // SQR_ENONFINITE
-  } else if ((a.mode == 0) ? (a.phase >= a.min_passes && err < a.tol) : (err < a.tol)) {
+  } else if ((a.mode == 0) ? (!cur32 && a.phase >= a.min_passes && err < a.tol) : (err < a.tol)) {
     status = 0;
   } else if (a.phase >= a.max_iter) {
     status = 1;  // SQR_NOT_CONVERGED
@@ -938,14 +982,18 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     const double mm = (double)a.m;
     const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
                                      : (mm * q + (double)q * (q + 1));
-    sigma = fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
+    // FP32 Gramian (mixed form): sigma = p u32 ||X||, floor 2 u32
+    constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+    const double ufl = cur32 ? kU32 : a.u;
+    sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
+                  : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
     for (int esc = 0;; ++esc) {
       fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
       ++attempts;
       ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_blocked(M, p, mlo);
       if (ok) break;
       if (esc >= a.max_escalations) break;
-      sigma = fmax(10.0 * sigma, 2.0 * a.u);
+      sigma = fmax(10.0 * sigma, 2.0 * ufl);
     }
     if (!ok) {
       if (tid == 0) {
@@ -1101,6 +1149,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   }
   if (tid == 0) {
     c->passes = pass;
+    c->gram32 = (cur32 && shifted) ? 1 : 0;   // FP32 Gramians end after an unshifted pass
     if (pass <= 16) c->sigma[pass - 1] = sigma;
     c->chol_attempts = prev_att + attempts;
     c->orth_fro = err;

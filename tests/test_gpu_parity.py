@@ -268,3 +268,27 @@ def test_append_growth_parity_full_1e6():
     assert sum(abs(x - y) for x, y in zip(orc, gp)) <= 2
     rows = np.random.default_rng(0).choice(A.shape[0], 2000, replace=False)
     assert np.max(np.abs(Qg[rows, :10] - Qo[rows, :10])) <= 1e-8 * np.max(np.abs(Qo[:, :10]))
+
+
+@pytest.mark.parametrize("m,n", [(6000, 10), (6000, 16), (5000, 64), (4001, 128)])
+@pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
+def test_orth_mixed_parity(m, n, kappa):
+    """Mixed FP32/FP64 form against the oracle's mixed form and the FP64 QR."""
+    A = S.test_matrix(m, n, kappa, seed=(13,))
+    Qo, Ro, io = O.orth(A)
+    Qm, Rm, im = O.orth(A, precision=1)
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(precision=1))
+    assert info["status"] == 0
+    assert abs(info["passes"] - im["passes"]) <= 1
+    # ||A||_2 = 1: the first (FP32) shift is n u32 to the norm estimate's accuracy
+    assert abs(info["sigma"][0] / (n * 2.0 ** -24) - 1.0) < 2e-2
+    assert info["sigma"][info["passes"] - 1] == 0.0
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+def test_orth_mixed_limits():
+    A = dev(S.test_matrix(1000, 130, 10.0, seed=(14,)))
+    with pytest.raises(RuntimeError):
+        sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=1))
+    with pytest.raises(RuntimeError):
+        sq.sqr_orth(A[:, :20], opts=sq.sqr_default_opts(precision=2))
