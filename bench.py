@@ -77,10 +77,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB first (counter calibration)")
+    ap.add_argument("--workload", choices=["growth", "serve"], default="growth",
+                    help="growth: the basis-growth step (default); serve: the serving loop")
+    ap.add_argument("--requests", type=int, default=10000, help="serve: requests")
+    ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
+    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent streams")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serve: arrivals per second (0: 0.8 x the measured saturated rate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "serve":
+        return serve_main(args)
 
     import numpy as np
     import torch
@@ -189,6 +198,79 @@ def main():
         "loo": loo, "ok": all(s == 0 for s in statuses) and loo <= 1e-12,
         "passes": [i["passes"] for i in all_infos[-1]],
         "gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(out))
+
+
+def serve_main(args):
+    """Serving workload: Poisson arrivals of orthogonalise / append requests
+    from many resident sessions (m log-uniform 1e4..2e6, n 8..256, p 1..16,
+    kappa log-uniform 1e2..1e12).  value = aggregate algorithmic GB/s over the
+    makespan; p50 / p99 latency beside it."""
+    import torch
+    from paper_2507_07788_amd import serve
+
+    reqs = serve.synthetic_workload(args.requests, args.sessions)
+    # saturated rate: a calibration batch of whole sessions, all arriving at once
+    cal_sessions = set(range(min(16, args.sessions)))
+    cal = [serve.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs if r.session in cal_sessions]
+    cres = serve.Server(workers=args.workers).run(cal)
+    csum = serve.summarize(cres)
+    rate = args.rate if args.rate > 0 else 0.8 * csum["req_per_s"]
+    serve.poisson_arrivals(reqs, rate)
+    torch.cuda.synchronize()
+    res = serve.Server(workers=args.workers).run(reqs)
+    summ = serve.summarize(res)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        from oracle import cholqr as O
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        # a sample: the requests of the first sessions in order, about 20 s of work
+        sample = sorted((r for r in reqs if r.session < 4), key=lambda r: r.rid)
+        byt, done, cdt = 0.0, 0, 0.0
+        state = {}
+        for r in sample:
+            if cdt > 20.0:
+                break
+            X = serve.make_input(r, 1_000_003 * (r.rid + 1)).cpu().numpy()   # not timed
+            ts = time.perf_counter()
+            if r.kind == "orth":
+                Qo, Ro, io = O.orth(X)
+                state[r.session] = Qo, Ro
+                q = 0
+            else:
+                Qi, Ri = state[r.session]
+                q = Qi.shape[1]
+                Qo, Ro, io = O.append(Qi, Ri, X)
+                if io["status"] == 0:
+                    state[r.session] = Qo, Ro
+            cdt += time.perf_counter() - ts
+            byt += serve.request_bytes(r.kind, r.m, q, r.cols, io["passes"])
+            done += 1
+        cpu = {"value": round(byt / cdt / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+               "sample": f"{done} requests of sessions 0-3 run in order on the host, {cdt:.1f} s"}
+
+    out = {
+        "metric": METRIC, "value": summ["GBs"], "unit": "GB/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(summ["makespan_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} requests from {args.sessions} sessions, "
+                               f"Poisson arrivals at {rate:.1f}/s (0.8 x saturated), "
+                               f"{args.workers} streams",
+                   "requests": args.requests, "sessions": args.sessions,
+                   "workers": args.workers, "rate_per_s": round(rate, 2)},
+        "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+        "req_per_s": summ["req_per_s"], "ok": summ["ok"],
+        "saturated": csum,
+        "roofline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

@@ -130,6 +130,16 @@ int64_t sqr_cols(const sqr_basis* b);
  * Caller buffers are not touched.  NULL is a no-op. */
 void sqr_free(sqr_basis* b);
 
+/* Return the handle's workspace (partial-Gramian slots, small-matrix arena,
+ * pinned state) to the library's pool once the work on its stream has ended,
+ * keeping the handle, its basis width and its last outcome (sqr_last_info
+ * still answers).  The next sqr_append takes a workspace from the pool again
+ * (or allocates one).  For servers that keep many bases resident between
+ * calls: idle handles then hold no scratch memory.  The pool keeps at most 16
+ * workspaces per process, releasing the smallest first.
+ * Returns SQR_OK, SQR_ENULL or SQR_EHIP (the stream reported an error). */
+int sqr_park(sqr_basis* b);
+
 #ifdef __cplusplus
 }
 #endif

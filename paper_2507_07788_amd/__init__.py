@@ -63,6 +63,8 @@ def _load():
     lib.sqr_cols.restype = I64
     lib.sqr_free.argtypes = [P]
     lib.sqr_free.restype = None
+    lib.sqr_park.argtypes = [P]
+    lib.sqr_park.restype = I32
     lib.sqr_prof_enable.argtypes = [I32]
     lib.sqr_prof_enable.restype = None
     lib.sqr_prof_read.argtypes = [ctypes.POINTER(SqrProf)]
@@ -167,6 +169,14 @@ def sqr_free(b: Basis) -> None:
     if b.handle:
         lib.sqr_free(b.handle)
         b.handle = None
+
+
+def sqr_park(b: Basis) -> None:
+    """Return the handle's workspace to the library pool (sqr_park)."""
+    if b.handle:
+        rc = lib.sqr_park(b.handle)
+        if rc < 0:
+            raise RuntimeError(f"sqr_park failed with code {rc}")
 
 
 def sqr_prof_enable(on: bool = True) -> None:

@@ -60,11 +60,39 @@ void prof_finalize(int64_t id, int passes) {
     if (r.call == id && r.real < 0) r.real = (r.phase <= passes) ? 1 : 0;
 }
 
-// ---- single-entry workspace cache: a freed handle's device buffers are kept
-// for the next handle on the same device that fits in them ----
+// ---- workspace pool: device buffers (and the pinned state) of freed or
+// parked handles are kept for later handles on the same device; at most
+// kPoolEntries are held, the smallest are released first ----
 std::mutex g_cache_mu;
 struct CachedWs { void* ptr = nullptr; size_t bytes = 0; int device = -1; void* pinned = nullptr; };
-CachedWs g_cache;
+std::vector<CachedWs> g_pool;
+constexpr size_t kPoolEntries = 16;
+
+bool pool_take(int device, size_t need, CachedWs* out) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  int best = -1;
+  for (int i = 0; i < (int)g_pool.size(); ++i)
+    if (g_pool[i].device == device && g_pool[i].bytes >= need &&
+        (best < 0 || g_pool[i].bytes < g_pool[best].bytes))
+      best = i;
+  if (best < 0) return false;
+  *out = g_pool[best];
+  g_pool.erase(g_pool.begin() + best);
+  return true;
+}
+
+void pool_put(const CachedWs& e) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_pool.push_back(e);
+  while (g_pool.size() > kPoolEntries) {
+    int small = 0;
+    for (int i = 1; i < (int)g_pool.size(); ++i)
+      if (g_pool[i].bytes < g_pool[small].bytes) small = i;
+    (void)hipFree(g_pool[small].ptr);
+    if (g_pool[small].pinned) (void)hipHostFree(g_pool[small].pinned);
+    g_pool.erase(g_pool.begin() + small);
+  }
+}
 
 int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
 int64_t nblocks(int64_t p) { return (p + 15) / 16; }
@@ -91,6 +119,8 @@ struct sqr_basis {
   int slots = 0;                     // partial-Gram slots (workgroups of block_pass)
   void* ws = nullptr;
   Ctrl* ctrl = nullptr;
+  Ctrl last{};                       // outcome of the last call (kept while parked)
+  bool parked = false;               // workspace returned to the pool
   Ctrl* ctrl_host = nullptr;         // pinned, written by small_step
   Ctrl* ctrl_host_dev = nullptr;     // its device address
   double *part = nullptr, *stage = nullptr;
@@ -223,11 +253,10 @@ int alloc_workspace(sqr_basis* b) {
   const size_t o_rinv = take(nblocks(cap) * 256);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
   {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    if (g_cache.ptr && g_cache.device == b->device && g_cache.bytes >= doubles * 8) {
-      b->ws = g_cache.ptr; b->ws_bytes = g_cache.bytes;
-      b->ctrl_host = (Ctrl*)g_cache.pinned;
-      g_cache = CachedWs();
+    CachedWs e;
+    if (pool_take(b->device, doubles * 8, &e)) {
+      b->ws = e.ptr; b->ws_bytes = e.bytes;
+      b->ctrl_host = (Ctrl*)e.pinned;
     }
   }
   if (!b->ws) {
@@ -508,6 +537,11 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stre
                sqr_info* info) {
   if (!b || !W) return SQR_ENULL;
   if (p < 1 || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m) return SQR_EDIM;
+  if (!b->ws) {   // parked: take a workspace again
+    const int rc0 = alloc_workspace(b);
+    if (rc0) return rc0;
+    b->parked = false;
+  }
   hipStream_t s = (hipStream_t)stream;
   Call c{1, b->n, p, W, ldw, b->Q + b->n * b->ldq, b->ldq};
   int rc = run_call(b, c, s, true, 2);
@@ -519,6 +553,10 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stre
 
 int sqr_last_info(sqr_basis* b, sqr_info* info) {
   if (!b || !info) return SQR_ENULL;
+  if (b->parked) {
+    fill_info(&b->last, info);
+    return info->status;
+  }
   if (fetch(b, b->stream)) return SQR_EHIP;
   if (g_prof_on) prof_finalize(b->call_id, b->ctrl_host->passes);
   fill_info(b->ctrl_host, info);
@@ -529,24 +567,26 @@ int64_t sqr_cols(const sqr_basis* b) { return b ? b->n : 0; }
 
 void sqr_free(sqr_basis* b) {
   if (!b) return;
-  if (b->stream || b->ws) (void)hipStreamSynchronize(b->stream);
+  (void)sqr_park(b);
+  delete b;
+}
+
+int sqr_park(sqr_basis* b) {
+  if (!b) return SQR_ENULL;
+  if (!b->ws && !b->ctrl_host) return SQR_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return SQR_EHIP;
+  if (b->ctrl_host) b->last = *b->ctrl_host;   // outcome of the last call
+  b->parked = true;
   if (b->ws) {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    if (g_cache.ptr && g_cache.bytes >= b->ws_bytes) {
-      (void)hipFree(b->ws);
-      if (b->ctrl_host) (void)hipHostFree(b->ctrl_host);
-    } else {
-      if (g_cache.ptr) {
-        (void)hipFree(g_cache.ptr);
-        if (g_cache.pinned) (void)hipHostFree(g_cache.pinned);
-      }
-      g_cache.ptr = b->ws; g_cache.bytes = b->ws_bytes; g_cache.device = b->device;
-      g_cache.pinned = b->ctrl_host;
-    }
+    CachedWs e;
+    e.ptr = b->ws; e.bytes = b->ws_bytes; e.device = b->device; e.pinned = b->ctrl_host;
+    pool_put(e);
   } else if (b->ctrl_host) {
     (void)hipHostFree(b->ctrl_host);
   }
-  delete b;
+  b->ws = nullptr; b->ws_bytes = 0; b->ctrl_host = nullptr; b->ctrl_host_dev = nullptr;
+  b->ctrl = nullptr; b->part = b->stage = b->X = b->bneg = b->rinv = nullptr;
+  return SQR_OK;
 }
 
 void sqr_prof_enable(int on) {

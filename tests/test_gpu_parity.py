@@ -292,3 +292,28 @@ def test_orth_mixed_limits():
         sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=1))
     with pytest.raises(RuntimeError):
         sq.sqr_orth(A[:, :20], opts=sq.sqr_default_opts(precision=2))
+
+
+def test_serving_mix_matches_each_session_alone():
+    """Serving loop: every session's final basis from a concurrent mix (four
+    streams, Poisson arrivals) equals the basis of the same session's requests
+    run alone on one stream, to the bit: kernel results do not depend on what
+    else runs on the device."""
+    from paper_2507_07788_amd import serve
+    reqs = serve.synthetic_workload(48, 8, seed=21, m_range=(3000, 40000),
+                                    n_range=(8, 40), p_range=(1, 16))
+    serve.poisson_arrivals(reqs, 1e5, seed=22)       # all but at once: streams overlap
+    mixed = {}
+    keep = {s: (lambda s: lambda Q, R: mixed.__setitem__(s, (Q, R)))(s) for s in range(8)}
+    res = serve.Server(workers=4, keep=keep).run(reqs)
+    assert len(res) == 48 and all(r.status == 0 for r in res)
+    assert any(a.start < b.end and b.start < a.end for a in res for b in res if a.rid != b.rid)
+    for s in range(8):
+        alone = {}
+        mine = [serve.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs if r.session == s]
+        serve.Server(workers=1, keep={s: lambda Q, R: alone.__setitem__(0, (Q, R))}).run(
+            mine, seeds={r.rid: 1_000_003 * (r.rid + 1) for r in mine})
+        Qm, Rm = mixed[s]
+        Qa, Ra = alone[0]
+        assert torch.equal(Qm, Qa) and torch.equal(Rm, Ra), s
+        assert O.loo(Qm.numpy()) <= 1e-12
