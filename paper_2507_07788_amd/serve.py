@@ -29,6 +29,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import sys
 import threading
 import time
 
@@ -186,8 +187,9 @@ class Server:
     (used by tests)."""
 
     def __init__(self, workers: int = 4, budget_bytes: float | None = None,
-                 lookahead_bytes: float = 8e9, opts=None, keep=None):
+                 lookahead_bytes: float = 8e9, opts=None, keep=None, progress: int = 0):
         self.workers = workers
+        self.progress = progress   # print a line to stderr every `progress` results
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = 0.85 * free - 8e9
@@ -288,6 +290,9 @@ class Server:
                 del X
                 self.results.append(res)
                 self.remaining -= 1
+                if self.progress and len(self.results) % self.progress == 0:
+                    print(f"served {len(self.results)} requests, {end:.1f} s",
+                          file=sys.stderr, flush=True)
                 last = not sess.queue
                 if last:
                     if r.session in self.keep and sess.basis is not None:
