@@ -191,8 +191,8 @@ class Server:
         self.workers = workers
         self.progress = progress   # print a line to stderr every `progress` results
         if budget_bytes is None:
-            free, _ = torch.cuda.mem_get_info()
-            budget_bytes = 0.85 * free - 8e9
+            _, total = torch.cuda.mem_get_info()
+            budget_bytes = 0.85 * total - 8e9
         self.budget = budget_bytes
         self.lookahead = lookahead_bytes
         self.opts = opts if opts is not None else sqr_default_opts()
@@ -230,14 +230,16 @@ class Server:
             r = sess.queue[0]
             if r.arrival > now or r.rid not in self.inputs:
                 continue
-            grow = 0
+            grow = 0                   # an append needs no new resident memory
             if r.kind == "orth":
                 grow = 8 * (r.m * r.cap + r.cap * r.cap) - sess.bytes
-            if self.resident + grow > self.budget and self.resident > 0:
+            # admit when it fits, and always when nothing is in flight (progress)
+            if grow > 0 and self.resident + grow > self.budget and self.in_flight > 0:
                 continue
             sess.queue.popleft()
             sess.busy = True
-            self.resident += max(grow, 0)
+            self.resident += grow
+            self.in_flight += 1
             return r, grow
         return None
 
@@ -305,6 +307,7 @@ class Server:
                     sess.bytes = 0
                     self.active.discard(r.session)
                 sess.busy = False
+                self.in_flight -= 1
                 self.cv.notify_all()
 
     def run(self, reqs, seeds=None):
@@ -322,6 +325,7 @@ class Server:
         self.inputs = {}
         self.results = []
         self.resident = 0
+        self.in_flight = 0
         self.inflight_inputs = 0.0
         self.remaining = len(reqs)
         self.stop = False

@@ -60,3 +60,28 @@ def test_usage_errors_before_any_gpu_work(sq):
     assert sq.lib.sqr_append(None, ctypes.c_void_p(0x1000), 1, 1, None, None) == sq.SQR_ENULL
     assert sq.lib.sqr_cols(None) == 0
     sq.lib.sqr_free(None)
+
+
+def test_serving_workload_recipe():
+    """The serving workload's request plan (host logic, no GPU): sessions
+    start with an orthogonalisation, reserve exactly the columns their
+    appends need, never exceed 512 columns, and keep their order."""
+    from paper_2507_07788_amd import serve
+    reqs = serve.synthetic_workload(2000, 64)
+    assert len(reqs) == 2000 and len({r.session for r in reqs}) == 64
+    width, cap, seen = {}, {}, set()
+    for r in sorted(reqs, key=lambda r: r.rid):
+        if r.session not in seen:
+            assert r.kind == "orth"
+            seen.add(r.session)
+        if r.kind == "orth":
+            width[r.session], cap[r.session] = r.cols, r.cap
+            assert r.cols <= r.cap <= 512 and r.cols <= r.m
+        else:
+            width[r.session] += r.cols
+            assert width[r.session] <= cap[r.session]
+            assert 1 <= r.cols <= 16
+    serve.poisson_arrivals(reqs, 100.0)
+    arr = [r.arrival for r in sorted(reqs, key=lambda r: r.rid)]
+    assert all(b > a for a, b in zip(arr, arr[1:]))
+    assert abs(arr[-1] / len(arr) - 0.01) < 0.002      # mean gap 1 / rate
