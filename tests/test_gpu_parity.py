@@ -317,3 +317,59 @@ def test_serving_mix_matches_each_session_alone():
         Qa, Ra = alone[0]
         assert torch.equal(Qm, Qa) and torch.equal(Rm, Ra), s
         assert O.loo(Qm.numpy()) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# full sizes of the measured configurations (m = 4e6 and 2e7 rows)
+# --------------------------------------------------------------------------
+def _invariants_dev(A, Q, R, n):
+    """LOO and RRR evaluated on the device in row blocks (any size)."""
+    m = A.shape[0]
+    G = torch.zeros((n, n), dtype=torch.float64, device=A.device)
+    res = nrm = 0.0
+    Rt = torch.triu(R[:n, :n]).contiguous()
+    for r0 in range(0, m, 1 << 22):
+        r1 = min(m, r0 + (1 << 22))
+        Qb = Q[r0:r1, :n].contiguous()
+        Ab = A[r0:r1].contiguous()
+        G += Qb.t() @ Qb
+        D = Ab - Qb @ Rt
+        res += float((D * D).sum())
+        nrm += float((Ab * Ab).sum())
+    loo = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
+    return loo, math.sqrt(res / nrm)
+
+
+@pytest.mark.slow
+def test_orth_full_size_m4e6_n64_against_oracle():
+    """m = 4e6, n = 64, kappa = 1e4: the oracle runs at full size on the host."""
+    A = S.test_matrix(4_000_000, 64, 1e4, seed=(3,))
+    Qo, Ro, io = O.orth(A)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0 and abs(info["passes"] - io["passes"]) <= 1
+    Rg = host(b.r())
+    assert np.max(np.abs(Rg - Ro)) <= 1e-10 * 1e4 * np.max(np.abs(Ro))
+    rows = np.random.default_rng(1).choice(A.shape[0], 4000, replace=False)
+    Qg = b.q()[torch.as_tensor(rows, device=b.Q.device)].cpu().numpy()
+    assert np.max(np.abs(Qg - Qo[rows])) <= 1e-10 * 1e4 * np.max(np.abs(Qo[rows]))
+    loo, rrr = _invariants_dev(dev(A), b.Q, b.R, 64)
+    assert loo <= 1e-12 and rrr <= 1e-13
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [0, 1])
+def test_orth_full_size_m4e6_n128_kappa1e12(precision):
+    A = S.test_matrix_device(4_000_000, 128, 1e12, (3,))
+    b, info = sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=precision))
+    assert info["status"] == 0
+    loo, rrr = _invariants_dev(A, b.Q, b.R, 128)
+    assert loo <= 1e-12 and rrr <= 1e-13
+
+
+@pytest.mark.slow
+def test_orth_full_size_m2e7_n256_kappa1e15():
+    A = S.test_matrix_device(20_000_000, 256, 1e15, (3,))
+    b, info = sq.sqr_orth(A)
+    assert info["status"] == 0 and info["passes"] <= 10
+    loo, rrr = _invariants_dev(A, b.Q, b.R, 256)
+    assert loo <= 1e-12 and rrr <= 1e-13
