@@ -373,3 +373,27 @@ def test_orth_full_size_m2e7_n256_kappa1e15():
     assert info["status"] == 0 and info["passes"] <= 10
     loo, rrr = _invariants_dev(A, b.Q, b.R, 256)
     assert loo <= 1e-12 and rrr <= 1e-13
+
+
+def test_orth_maximum_width_528():
+    """The widest basis a handle supports (33 blocks: per-block launches, the
+    small matrices in workspace memory)."""
+    A = S.test_matrix(3000, 528, 1e4, seed=(23,))
+    Qo, Ro, io = O.orth(A)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0 and abs(info["passes"] - io["passes"]) <= 1
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e4)
+
+
+def test_append_fills_capacity_528():
+    """Appends up to the 528-column capacity; one more column is refused."""
+    A = S.test_matrix(2500, 528, 1e3, seed=(24,))
+    b, info = sq.sqr_orth(dev(A[:, :400]), cap=528)
+    for c0 in range(400, 528, 64):
+        info = sq.sqr_append(b, dev(A[:, c0:c0 + 64]))
+        assert info["status"] == 0
+    assert b.n == 528
+    Qo, Ro, _ = O.orth(A)
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e3)
+    with pytest.raises(RuntimeError):
+        sq.sqr_append(b, dev(A[:, :1]))
