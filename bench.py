@@ -10,7 +10,7 @@ value = algorithmic HBM bytes of the step / time, where a CholQR pass count x
 costs (1 + 2x) m n 8 bytes and an append with x iterations costs
 8 m [(q + p) + x (q + 2p)] bytes (x = the passes the device executed).
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: this program runs on one GPU.
 """
 from __future__ import annotations
 
@@ -86,7 +86,7 @@ def main():
                     help="serve: arrivals per second (0: 0.8 x the measured saturated rate)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "serve":
         return serve_main(args)

@@ -25,7 +25,7 @@ Readings of the paper taken here (each one is also listed in the design notes):
     as "not converged".
 
 The mixed-precision form of ``orth`` (``precision=1``) is not in the paper;
-it follows this build's reading: Gramians of the shifted passes and of the
+it follows the reading taken here: Gramians of the shifted passes and of the
 first unshifted pass are formed from the FP32-rounded iterate with FP32
 accumulation, everything else (applies, shift estimate, Cholesky, the Gramian
 that feeds the final pass and the stopping test) stays FP64.  An FP32 Gramian

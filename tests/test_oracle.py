@@ -434,7 +434,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
 # ---------------------------------------------------------------------------
 # mixed-precision form (precision=1): FP32 Gramians until the first unshifted
-# pass, then FP64 (a reading of this build; the paper has no mixed form)
+# pass, then FP64 (a reading taken here; the paper has no mixed form)
 # ---------------------------------------------------------------------------
 def test_shift_fp32_exact():
     assert O.shift_fp32(16, 1.0) == 16 * 2.0 ** -24
