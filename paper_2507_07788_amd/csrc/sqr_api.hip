@@ -155,6 +155,19 @@ const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
                              SQR_WIDE(5), SQR_WIDE(6), SQR_WIDE(7), SQR_WIDE(8)};
 #undef SQR_WIDE
 int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
+
+// Orth calls of 9..16 blocks: a whole-pass apply and a Gramian kernel.
+typedef void (*SplitKernel)(WidePassArgs);
+struct SplitVariant { SplitKernel apply, gram; };
+#define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB>}
+constexpr int kSplitMin = 9, kSplitMax = 16;
+const SplitVariant kSplit[] = {SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_SPLIT(12),
+                               SQR_SPLIT(13), SQR_SPLIT(14), SQR_SPLIT(15), SQR_SPLIT(16)};
+#undef SQR_SPLIT
+int g_split_occ[2][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply][nb]
+size_t split_lds_bytes(int nb, bool apply) {
+  return 8 * (size_t)(apply ? apply_stage_doubles(nb) : gram_op_doubles(nb));
+}
 size_t wide_lds_bytes(int nb, bool apply) {
   return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));
 }
@@ -190,6 +203,12 @@ void set_kernel_attributes() {
         (void)hipFuncSetAttribute((const void*)kWide[nb - kWideMin].k[g32][ap],
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)wide_lds_bytes(nb, ap != 0));
+  for (int nb = kSplitMin; nb <= kSplitMax; ++nb) {
+    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].apply,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, true));
+    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].gram,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, false));
+  }
   (void)hipGetLastError();
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -219,6 +238,20 @@ void set_kernel_attributes() {
           n = 1;
         g_wide_occ[g32][ap][nb - kWideMin] = n;
       }
+  for (int nb = kSplitMin; nb <= kSplitMax; ++nb) {
+    int n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kSplit[nb - kSplitMin].apply,
+                                                      kThreads, split_lds_bytes(nb, true)) != hipSuccess ||
+        n < 1)
+      n = 1;
+    g_split_occ[1][nb - kSplitMin] = n;
+    n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kSplit[nb - kSplitMin].gram,
+                                                      kGramThreads, split_lds_bytes(nb, false)) != hipSuccess ||
+        n < 1)
+      n = 1;
+    g_split_occ[0][nb - kSplitMin] = n;
+  }
   g_attr_done = true;
 }
 
@@ -295,7 +328,54 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   const bool apply = phase > 0;
   int64_t nwg = b->slots;
   const bool mixed = c.mode == 0 && b->opts.precision == 1;
-  if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
+  if (c.mode == 0 && !mixed && P >= kSplitMin && P <= kSplitMax) {
+    // apply (from pass 1 on), then the Gramian of its result
+    const int idx = (int)P - kSplitMin;
+    const int64_t steps = (tiles + kWaves - 1) / kWaves;
+    WidePassArgs w;
+    memset(&w, 0, sizeof(w));
+    w.n = (int)c.p; w.m = b->m;
+    w.bneg = b->bneg; w.rinv = b->rinv;
+    w.part = b->part; w.part_stride = tl;
+    w.done = phase > 0 ? &b->ctrl->done : nullptr;
+    w.passes = &b->ctrl->passes;
+    auto launch = [&](const void* k, int64_t grid, int threads, size_t lds, int kind, double bytes) {
+      void* args[] = {&w};
+      ProfRec rec{};
+      if (g_prof_on) {
+        rec.e0 = take_event(); rec.e1 = take_event();
+        rec.kind = kind; rec.bytes = bytes;
+        rec.call = b->call_id; rec.phase = phase; rec.real = -1;
+        if (rec.e0) (void)hipEventRecord(rec.e0, s);
+      }
+      if (hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), args, lds, s) != hipSuccess)
+        return false;
+      if (g_prof_on && rec.e0 && rec.e1) {
+        (void)hipEventRecord(rec.e1, s);
+        g_prof.push_back(rec);
+      }
+      return true;
+    };
+    if (apply) {
+      w.win = (phase > 1) ? c.y : c.win;
+      w.ldw = (phase > 1) ? c.ldy : c.ldw;
+      w.yout = c.y; w.ldy = c.ldy;
+      w.copy_if_done = (phase == 1);
+      const int64_t ga = std::max<int64_t>(1, std::min<int64_t>((int64_t)g_ncu * g_split_occ[1][idx], steps));
+      if (!launch((const void*)kSplit[idx].apply, ga, kThreads, split_lds_bytes((int)P, true), 1,
+                  16.0 * (double)b->m * (double)c.p))
+        return SQR_EHIP;
+    }
+    // the Gramian of the pass's result (of the input at phase 0)
+    w.win = apply ? c.y : c.win;
+    w.ldw = apply ? c.ldy : c.ldw;
+    w.copy_if_done = 0;
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_split_occ[0][idx]);
+    nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, steps));
+    if (!launch((const void*)kSplit[idx].gram, nwg, kGramThreads, split_lds_bytes((int)P, false), 0,
+                8.0 * (double)b->m * (double)c.p))
+      return SQR_EHIP;
+  } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
     // precision from pass 1 on; the one that does not match the device's
     // choice exits at once)

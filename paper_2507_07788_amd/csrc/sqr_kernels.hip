@@ -580,6 +580,239 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Orth calls of 9..16 blocks (129..256 columns): the apply and the Gramian
+// of a pass as two launches.  Registers cannot hold a row tile of Y, the
+// prefetched input and all Gramian accumulators at once, so
+//   wide_apply<NB>: Y = W R~^{-1} with the row tile's Y blocks in registers
+//     (as in wide_pass) and the panel [C_J; D_J] of block J staged through
+//     LDS while block J-1 is formed (one barrier per block);
+//   gram_pass<NB>:  the Gramian of the m x n result (upper 16x16 blocks),
+//     eight waves, 64-row steps staged in LDS in MFMA operand order, the
+//     blocks (I, J) dealt out to the waves; also the initial Gramian of A.
+// The pass then reads the tall data three times (W, and Y twice) instead of
+// re-reading the prefix Y_<J for every block.
+// ---------------------------------------------------------------------------
+constexpr int kGramWaves = 8;
+constexpr int kGramThreads = 64 * kGramWaves;
+__host__ __device__ constexpr int gram_op_doubles(int nb) { return kWaves * nb * 4 * kOpSlot; }
+__host__ __device__ constexpr int apply_stage_doubles(int nb) { return 2 * 256 * nb; }
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t s1 = min(steps, s0 + per);
+
+  if (a.done && *a.done) {
+    if (a.copy_if_done && *a.passes == 0) {
+      for (int64_t t = s0 * kWaves + wave; t < min(tiles, s1 * kWaves); t += kWaves) {
+        const int64_t row = t * 16 + x;
+        if (row >= a.m) continue;
+        for (int c = g; c < a.n; c += 4)
+          a.yout[(int64_t)c * a.ldy + row] = a.win[(int64_t)c * a.ldw + row];
+      }
+    }
+    return;
+  }
+
+  // Blocks [J0, J1) of one tile in D layout (columns past n read zero, rows
+  // past m are masked).
+  auto load_w = [&](int64_t tile, d4* w, int J0, int J1) {
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = row < a.m;
+    const int64_t rowc = row_ok ? row : a.m - 1;
+    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+#pragma unroll
+    for (int J = J0; J < J1; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c0 = 16 * J + 4 * r;
+        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+        const uint64_t bits = __builtin_bit_cast(uint64_t,
+            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+        w[J - J0][r] = __builtin_bit_cast(double, bits & keep);
+      }
+  };
+  // panel J = [C_J (16 J rows); D_J (16 rows)] x 16, row-major: a thread
+  // loads its (at most NB) elements into registers first and stores them to
+  // LDS buffer b later, so the loads are in flight during the MFMA work
+  auto stage_load = [&](int J, double (&v)[NB]) {
+    const double* C = a.bneg + 128 * J * (J - 1);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = threadIdx.x + kThreads * i;
+      v[i] = (e < 256 * J) ? C[e] : (e < 256 * (J + 1) ? a.rinv[256 * J + e - 256 * J] : 0.0);
+    }
+  };
+  auto stage_store = [&](int J, int b, const double (&v)[NB]) {
+    double* P = lds + b * 256 * NB;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = threadIdx.x + kThreads * i;
+      if (e < 256 * (J + 1)) P[e] = v[i];
+    }
+  };
+
+  // The next tile's first NPF blocks are prefetched; the rest of a tile is
+  // loaded at the start of its step, behind the MFMA work of the first blocks
+  // (registers hold the tile's Y blocks and the prefetch, not two tiles).
+  constexpr int NPF = NB <= 10 ? NB : (NB <= 12 ? 6 : 4);
+  d4 wnext[NPF];
+  load_w(min(s0 * kWaves + wave, tiles - 1), wnext, 0, NPF);
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t tile = s * kWaves + wave;
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = tile < tiles && row < a.m;
+    d4 y[NB];
+#pragma unroll
+    for (int J = 0; J < NPF; ++J) y[J] = wnext[J];
+    if (NPF < NB) load_w(min(tile, tiles - 1), y + NPF, NPF, NB);
+    load_w(min(tile + kWaves, tiles - 1), wnext, 0, NPF);
+    __syncthreads();          // the previous step has finished with both buffers
+    {
+      double v0[NB];
+      stage_load(0, v0);
+      stage_store(0, 0, v0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int J = 0; J < NB; ++J) {
+      // keep the scheduler from hoisting later blocks' operand loads into
+      // this block (their registers would not fit beside the tile's Y)
+      __builtin_amdgcn_sched_barrier(0);
+      double vn[NB];
+      if (J + 1 < NB) stage_load(J + 1, vn);
+      const double* P = lds + (J & 1) * 256 * NB;
+      d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
+      d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
+      c0 = mfma(P[(16 * J + g) * 16 + x], y[J][0], c0);
+      c1 = mfma(P[(16 * J + 4 + g) * 16 + x], y[J][1], c1);
+      c0 = mfma(P[(16 * J + 8 + g) * 16 + x], y[J][2], c0);
+      c1 = mfma(P[(16 * J + 12 + g) * 16 + x], y[J][3], c1);
+#pragma unroll
+      for (int I = 0; I < J; ++I) {
+        if ((I & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the operand loads in flight
+        c0 = mfma(P[(16 * I + g) * 16 + x], y[I][0], c0);
+        c1 = mfma(P[(16 * I + 4 + g) * 16 + x], y[I][1], c1);
+        c0 = mfma(P[(16 * I + 8 + g) * 16 + x], y[I][2], c0);
+        c1 = mfma(P[(16 * I + 12 + g) * 16 + x], y[I][3], c1);
+      }
+      y[J] = row_ok ? (c0 + c1) : d4{0.0, 0.0, 0.0, 0.0};
+      if (row_ok) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * J + g + 4 * r;
+          if (col < a.n) a.yout[(int64_t)col * a.ldy + row] = y[J][r];
+        }
+      }
+      if (J + 1 < NB) stage_store(J + 1, (J + 1) & 1, vn);
+      __syncthreads();        // panel J + 1 staged, panel J free
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
+  extern __shared__ double lds[];
+  constexpr int NP = NB * (NB + 1) / 2;
+  constexpr int KP = (NP + kGramWaves - 1) / kGramWaves;
+  constexpr int H = (NB + 1) / 2;                 // blocks loaded per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tw = wave >> 1, half = wave & 1;      // row tile of the step, half of the blocks
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t s1 = min(steps, s0 + per);
+  if (a.done && *a.done) return;
+
+  auto load_h = [&](int64_t tile, d4 (&w)[H]) {
+    const int64_t row = tile * 16 + x;
+    const bool row_ok = row < a.m;
+    const int64_t rowc = row_ok ? row : a.m - 1;
+    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c0 = 16 * (half * H + jj) + 4 * r;
+        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+        const uint64_t bits = __builtin_bit_cast(uint64_t,
+            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+        w[jj][r] = __builtin_bit_cast(double, bits & keep);
+      }
+  };
+
+  d4 acc[KP];
+  int pi[KP], pj[KP];
+  bool pok[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    const int pidx = wave + kGramWaves * k;
+    pok[k] = pidx < NP;
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= pidx && J < NB - 1) ++J;
+    pj[k] = J;
+    pi[k] = min(pidx - J * (J + 1) / 2, J);
+  }
+
+  d4 wnext[H];
+  load_h(min(s0 * kWaves + tw, tiles - 1), wnext);
+  double* myop = lds + tw * NB * 4 * kOpSlot;
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t tile = s * kWaves + tw;
+    const bool tile_ok = tile < tiles;
+    // this step's tile into LDS (operand order), then the next tile's loads
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) {
+      const int J = half * H + jj;
+      if (J < NB) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = tile_ok ? wnext[jj][r] : 0.0;
+      }
+    }
+    load_h(min(tile + kWaves, tiles - 1), wnext);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (pok[k]) {
+        const double* oa = lds + pi[k] * 4 * kOpSlot + x + 17 * g;
+        const double* ob = lds + pj[k] * 4 * kOpSlot + x + 17 * g;
+#pragma unroll
+        for (int t = 0; t < kWaves; ++t)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+      }
+    }
+    __syncthreads();
+  }
+  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (pok[k]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small_step: one workgroup of 1024 threads finishes a pass.
 // ---------------------------------------------------------------------------
 constexpr int kSmallThreads = 256;

@@ -99,7 +99,8 @@ def test_orth_parity_20000x20_kappa1e6():
 
 
 @pytest.mark.parametrize("m,n", [(1000, 5), (4099, 16), (10007, 17), (5000, 33),
-                                 (3001, 64), (2000, 100), (2500, 128), (4097, 113)])
+                                 (3001, 64), (2000, 100), (2500, 128), (4097, 113),
+                                 (2600, 200), (3001, 256)])
 @pytest.mark.parametrize("kappa", [1e2, 1e8, 1e12, 1e15])
 def test_orth_parity_sweep(m, n, kappa):
     A = S.test_matrix(m, n, kappa, seed=(3,))
@@ -121,7 +122,7 @@ def test_orth_algorithm1_literal_fig1_shape(e):
     assert O.rrr(A, host(b.q()), host(b.r())) <= 1e-13
 
 
-@pytest.mark.parametrize("m,n", [(3000, 70), (2000, 100), (2100, 128)])
+@pytest.mark.parametrize("m,n", [(3000, 70), (2000, 100), (2100, 128), (2200, 160)])
 def test_orth_breakdown_then_shift_wide(m, n):
     """Algorithm 1 as printed: the unshifted first factorisation of a kappa =
     1e15 Gramian breaks down and the shifted retry (power iteration, shift,
