@@ -166,7 +166,7 @@ const SplitVariant kSplit[] = {SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_S
 #undef SQR_SPLIT
 int g_split_occ[2][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply][nb]
 size_t split_lds_bytes(int nb, bool apply) {
-  return 8 * (size_t)(apply ? apply_stage_doubles(nb) : gram_op_doubles(nb));
+  return 8 * (size_t)(apply ? apply_lds_doubles(nb) : gram_op_doubles(nb));
 }
 size_t wide_lds_bytes(int nb, bool apply) {
   return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));

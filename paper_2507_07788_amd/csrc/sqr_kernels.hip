@@ -595,11 +595,32 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
 constexpr int kGramWaves = 8;
 constexpr int kGramThreads = 64 * kGramWaves;
 __host__ __device__ constexpr int gram_op_doubles(int nb) { return kWaves * nb * 4 * kOpSlot; }
-__host__ __device__ constexpr int apply_stage_doubles(int nb) { return 2 * 256 * nb; }
+
+// LDS doubles of wide_apply: panels 0..R-1 resident for the whole launch,
+// two stream buffers for the later panels (none when all fit).
+constexpr int kApplyLdsDoubles = 19968;   // 156 KB
+__host__ __device__ constexpr int apply_resident(int nb) {
+  int r = nb;
+  while (r > 0 && 128 * r * (r + 1) + (r < nb ? 2 * 256 * nb : 0) > kApplyLdsDoubles) --r;
+  return r;
+}
+__host__ __device__ constexpr int apply_lds_doubles(int nb) {
+  return 128 * apply_resident(nb) * (apply_resident(nb) + 1) +
+         (apply_resident(nb) < nb ? 2 * 256 * nb : 0);
+}
+
+// s_waitcnt with vmcnt(n) only (expcnt and lgkmcnt left at their maximum)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
   extern __shared__ double lds[];
+  constexpr int R = apply_resident(NB);           // resident panels
+  constexpr int NPF = NB <= 10 ? NB : 8;          // blocks of the next tile prefetched
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = lane & 15, g = lane >> 4;
@@ -621,52 +642,54 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
     return;
   }
 
-  // Blocks [J0, J1) of one tile in D layout (columns past n read zero, rows
-  // past m are masked).
-  auto load_w = [&](int64_t tile, d4* w, int J0, int J1) {
+  // Block J of one tile in D layout (columns past n read zero, rows past m
+  // are masked).
+  auto load_block = [&](int64_t tile, int J) -> d4 {
     const int64_t row = tile * 16 + x;
     const bool row_ok = row < a.m;
     const int64_t rowc = row_ok ? row : a.m - 1;
     const uint64_t keep = row_ok ? ~0ull : 0ull;
     const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+    d4 w;
 #pragma unroll
-    for (int J = J0; J < J1; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int c0 = 16 * J + 4 * r;
-        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
-        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
-        const uint64_t bits = __builtin_bit_cast(uint64_t,
-            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
-        w[J - J0][r] = __builtin_bit_cast(double, bits & keep);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int c0 = 16 * J + 4 * r;
+      const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+      const uint64_t bits = __builtin_bit_cast(uint64_t,
+          __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+      w[r] = __builtin_bit_cast(double, bits & keep);
+    }
+    return w;
   };
-  // panel J = [C_J (16 J rows); D_J (16 rows)] x 16, row-major: a thread
-  // loads its (at most NB) elements into registers first and stores them to
-  // LDS buffer b later, so the loads are in flight during the MFMA work
-  auto stage_load = [&](int J, double (&v)[NB]) {
-    const double* C = a.bneg + 128 * J * (J - 1);
+  // Panel J = [C_J (16 J rows); D_J (16 rows)] x 16, row-major (2 (J + 1)
+  // chunks of 1 KB).  Resident panels: plain loads at the start.  Streamed
+  // panels: direct global -> LDS loads, chunk c by wave c % 4, lane l moving
+  // 16 bytes to chunk base + 16 l; completion is awaited with vmcnt.
+  double* stream = lds + 128 * R * (R + 1);
+  auto panel_src = [&](int J, int c) -> const double* {
+    return (c < 2 * J) ? a.bneg + 128 * J * (J - 1) + 128 * c : a.rinv + 256 * J + 128 * (c - 2 * J);
+  };
+  auto dma_panel = [&](int J, double* dst) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + kThreads * i;
-      v[i] = (e < 256 * J) ? C[e] : (e < 256 * (J + 1) ? a.rinv[256 * J + e - 256 * J] : 0.0);
+    for (int i = 0; i < (2 * (J + 1) + kWaves - 1) / kWaves; ++i) {
+      const int c = wave + kWaves * i;
+      if (c < 2 * (J + 1))
+        __builtin_amdgcn_global_load_lds((const void*)(panel_src(J, c) + 2 * lane),
+                                         (__attribute__((address_space(3))) void*)(dst + 128 * c),
+                                         16, 0, 0);
     }
   };
-  auto stage_store = [&](int J, int b, const double (&v)[NB]) {
-    double* P = lds + b * 256 * NB;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int e = threadIdx.x + kThreads * i;
-      if (e < 256 * (J + 1)) P[e] = v[i];
-    }
-  };
+  for (int J = 0; J < R; ++J) {
+    double* P = lds + 128 * J * (J + 1);
+    for (int e = threadIdx.x; e < 256 * (J + 1); e += kThreads)
+      P[e] = (e < 256 * J) ? a.bneg[128 * J * (J - 1) + e] : a.rinv[256 * J + e - 256 * J];
+  }
+  __syncthreads();
 
-  // The next tile's first NPF blocks are prefetched; the rest of a tile is
-  // loaded at the start of its step, behind the MFMA work of the first blocks
-  // (registers hold the tile's Y blocks and the prefetch, not two tiles).
-  constexpr int NPF = NB <= 10 ? NB : (NB <= 12 ? 6 : 4);
   d4 wnext[NPF];
-  load_w(min(s0 * kWaves + wave, tiles - 1), wnext, 0, NPF);
+#pragma unroll
+  for (int J = 0; J < NPF; ++J) wnext[J] = load_block(min(s0 * kWaves + wave, tiles - 1), J);
   for (int64_t s = s0; s < s1; ++s) {
     const int64_t tile = s * kWaves + wave;
     const int64_t row = tile * 16 + x;
@@ -674,23 +697,26 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
     d4 y[NB];
 #pragma unroll
     for (int J = 0; J < NPF; ++J) y[J] = wnext[J];
-    if (NPF < NB) load_w(min(tile, tiles - 1), y + NPF, NPF, NB);
-    load_w(min(tile + kWaves, tiles - 1), wnext, 0, NPF);
-    __syncthreads();          // the previous step has finished with both buffers
-    {
-      double v0[NB];
-      stage_load(0, v0);
-      stage_store(0, 0, v0);
-    }
-    __syncthreads();
 #pragma unroll
+    for (int J = NPF; J < NB; ++J) y[J] = load_block(min(tile, tiles - 1), J);
+    if (R == NB) {
+#pragma unroll
+      for (int J = 0; J < NPF; ++J) wnext[J] = load_block(min(tile + kWaves, tiles - 1), J);
+    }
+#pragma clang loop unroll(full)
     for (int J = 0; J < NB; ++J) {
-      // keep the scheduler from hoisting later blocks' operand loads into
-      // this block (their registers would not fit beside the tile's Y)
+      // keep later blocks' operand loads out of this block (their registers
+      // would not fit beside the tile's Y)
       __builtin_amdgcn_sched_barrier(0);
-      double vn[NB];
-      if (J + 1 < NB) stage_load(J + 1, vn);
-      const double* P = lds + (J & 1) * 256 * NB;
+      const bool stage_next = J + 1 >= R && J + 1 < NB;
+      if (stage_next) dma_panel(J + 1, stream + ((J + 1) & 1) * 256 * NB);
+      // the next tile's prefetch goes out after the last streamed panel, so
+      // the panel waits below do not wait for it
+      if (R < NB && J == NB - 2) {
+#pragma unroll
+        for (int J2 = 0; J2 < NPF; ++J2) wnext[J2] = load_block(min(tile + kWaves, tiles - 1), J2);
+      }
+      const double* P = (J < R) ? lds + 128 * J * (J + 1) : stream + (J & 1) * 256 * NB;
       d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
       d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
       c0 = mfma(P[(16 * J + g) * 16 + x], y[J][0], c0);
@@ -699,7 +725,6 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
       c1 = mfma(P[(16 * J + 12 + g) * 16 + x], y[J][3], c1);
 #pragma unroll
       for (int I = 0; I < J; ++I) {
-        if ((I & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the operand loads in flight
         c0 = mfma(P[(16 * I + g) * 16 + x], y[I][0], c0);
         c1 = mfma(P[(16 * I + 4 + g) * 16 + x], y[I][1], c1);
         c0 = mfma(P[(16 * I + 8 + g) * 16 + x], y[I][2], c0);
@@ -713,9 +738,14 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
           if (col < a.n) a.yout[(int64_t)col * a.ldy + row] = y[J][r];
         }
       }
-      if (J + 1 < NB) stage_store(J + 1, (J + 1) & 1, vn);
-      __syncthreads();        // panel J + 1 staged, panel J free
+      if (stage_next) {
+        // this wave's chunks of panel J + 1 have landed (the prefetch issued
+        // after them may still be in flight), then all waves' chunks have
+        if (J == NB - 2 && R < NB) wait_vmcnt<4 * NPF>(); else wait_vmcnt<0>();
+        __syncthreads();
+      }
     }
+    if (R < NB) __syncthreads();   // the stream buffers are free for the next step
   }
 }
 
