@@ -160,8 +160,8 @@ int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 typedef void (*SplitKernel)(WidePassArgs);
 struct SplitVariant { SplitKernel apply, gram; };
 #define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB>}
-constexpr int kSplitMin = 9, kSplitMax = 16;
-const SplitVariant kSplit[] = {SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_SPLIT(12),
+constexpr int kSplitMin = 8, kSplitMax = 16;
+const SplitVariant kSplit[] = {SQR_SPLIT(8), SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_SPLIT(12),
                                SQR_SPLIT(13), SQR_SPLIT(14), SQR_SPLIT(15), SQR_SPLIT(16)};
 #undef SQR_SPLIT
 int g_split_occ[2][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply][nb]
