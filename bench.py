@@ -77,8 +77,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["growth", "serve"], default="growth",
-                    help="growth: the basis-growth step (default); serve: the serving loop")
+    ap.add_argument("--workload", choices=["growth", "serve", "orth"], default="growth",
+                    help="growth: the basis-growth step (default); serve: the serving loop; "
+                         "orth: one CholQR3 of an m x n matrix (--m, --n, --kappa, --precision)")
+    ap.add_argument("--n", type=int, default=128, help="orth: columns")
+    ap.add_argument("--kappa", type=float, default=1e12, help="orth: condition number")
+    ap.add_argument("--precision", type=int, default=0, help="orth: 0 FP64, 1 mixed")
     ap.add_argument("--requests", type=int, default=10000, help="serve: requests")
     ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent streams")
@@ -90,6 +94,8 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         return serve_main(args)
+    if args.workload == "orth":
+        return orth_main(args)
 
     import numpy as np
     import torch
@@ -198,6 +204,71 @@ def main():
         "loo": loo, "ok": all(s == 0 for s in statuses) and loo <= 1e-12,
         "passes": [i["passes"] for i in all_infos[-1]],
         "gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(out))
+
+
+def orth_main(args):
+    """One orthogonalisation (Algorithm 1 with the CholQR3 start) of a seeded
+    m x n matrix U diag(s) V^T with the given condition number, formed on the
+    device.  value = algorithmic GB/s of the call ((1 + 2x) m n words for x
+    passes); GFLOP/s counts (2x + 1) m n^2.  Invariants evaluated afterwards."""
+    import torch
+    import paper_2507_07788_amd as sq
+    import synth
+
+    m, n = args.m, args.n
+    A = synth.test_matrix_device(m, n, args.kappa, (3,))
+    Q = sq.colmajor(m, n)
+    R = sq.colmajor(n, n)
+    opts = sq.sqr_default_opts(precision=args.precision)
+    for _ in range(args.warmup):
+        b, info = sq.sqr_orth(A, opts=opts, Q=Q, R=R)
+        sq.sqr_free(b)
+    torch.cuda.synchronize()
+    sq.sqr_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b, info = sq.sqr_orth(A, opts=opts, Q=Q, R=R)
+        sq.sqr_free(b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    prof = sq.sqr_prof_read()
+    sq.sqr_prof_enable(False)
+    x = info["passes"]
+    byt = 8.0 * m * n * (1 + 2 * x)
+    fl = (2 * x + 1) * m * n * n
+    # invariants, in row blocks
+    G = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = nrm = 0.0
+    Rt = torch.triu(R).contiguous()
+    for r0 in range(0, m, 1 << 22):
+        r1 = min(m, r0 + (1 << 22))
+        Qb, Ab = Q[r0:r1].contiguous(), A[r0:r1].contiguous()
+        G += Qb.t() @ Qb
+        D = Ab - Qb @ Rt
+        res += float((D * D).sum())
+        nrm += float((Ab * Ab).sum())
+    loo = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
+    mfma = n >= 128
+    achieved = fl / dt / 1e12 if mfma else byt / dt / 1e9
+    peak = 78.6 if mfma else HBM_PEAK_GBS
+    out = {
+        "metric": METRIC, "value": round(byt / dt / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"orth {m}x{n}, kappa {args.kappa:g}, "
+                               f"{'mixed FP32/FP64' if args.precision else 'FP64'}",
+                   "m": m, "n": n, "kappa": args.kappa, "precision": args.precision},
+        "GFLOPs": round(fl / dt / 1e9, 1),
+        "roofline": {"bound": "mfma" if mfma else "hbm", "achieved": round(achieved, 2 if mfma else 1),
+                     "peak": peak, "unit": "TFLOP/s" if mfma else "GB/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "scope": "whole call (all kernels)"},
+        "passes": x, "status": info["status"], "loo": loo, "rrr": math.sqrt(res / nrm),
+        "kernels": {"apply": prof["apply"], "gram": prof["gram"]},
+        "cpu_baseline": None,
     }
     print(json.dumps(out))
 
