@@ -40,7 +40,7 @@ extern "C" {
  * (Sec. 3.1: tolerance 1e-13 on ||I - Q^T Q||_F, at most 10 iterations). */
 typedef struct sqr_opts {
   int32_t precision;        /* 0 = FP64 throughout.  1 = mixed form of sqr_orth
-                               (n <= 128): the Gramians of the shifted passes
+                               (n <= 256): the Gramians of the shifted passes
                                and of the first unshifted pass are formed on
                                FP32 MFMA from the FP32-rounded iterate; applies,
                                shift estimates, Cholesky and the Gramians of the
@@ -98,7 +98,7 @@ void sqr_default_opts(sqr_opts* o);
  * enqueued on `stream` completes.  The handle owns only its workspace.
  * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
  * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT (also for
- * precision 1 with n > 128), SQR_EHIP; all
+ * precision 1 with n > 256), SQR_EHIP; all
  * before any work is enqueued, except SQR_EHIP from a failed launch.
  */
 int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,

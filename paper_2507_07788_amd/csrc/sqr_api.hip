@@ -156,18 +156,20 @@ const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
 #undef SQR_WIDE
 int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 
-// Orth calls of 9..16 blocks: a whole-pass apply and a Gramian kernel.
+// Orth calls of 8..16 blocks: a whole-pass apply and a Gramian kernel
+// (FP64, and FP32 for the mixed form).
 typedef void (*SplitKernel)(WidePassArgs);
-struct SplitVariant { SplitKernel apply, gram; };
-#define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB>}
+struct SplitVariant { SplitKernel apply, gram, gram32; };
+#define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB, false>, gram_pass<NB, true>}
 constexpr int kSplitMin = 8, kSplitMax = 16;
 const SplitVariant kSplit[] = {SQR_SPLIT(8), SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_SPLIT(12),
                                SQR_SPLIT(13), SQR_SPLIT(14), SQR_SPLIT(15), SQR_SPLIT(16)};
 #undef SQR_SPLIT
-int g_split_occ[2][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply][nb]
+int g_split_occ[3][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply, 2 gram32][nb]
 size_t split_lds_bytes(int nb, bool apply) {
   return 8 * (size_t)(apply ? apply_lds_doubles(nb) : gram_op_doubles(nb));
 }
+size_t gram32_lds_bytes(int nb) { return 4 * (size_t)gram_op_doubles(nb); }
 size_t wide_lds_bytes(int nb, bool apply) {
   return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));
 }
@@ -208,6 +210,8 @@ void set_kernel_attributes() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, true));
     (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].gram,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, false));
+    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].gram32,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram32_lds_bytes(nb));
   }
   (void)hipGetLastError();
   int dev = 0;
@@ -251,6 +255,12 @@ void set_kernel_attributes() {
         n < 1)
       n = 1;
     g_split_occ[0][nb - kSplitMin] = n;
+    n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kSplit[nb - kSplitMin].gram32,
+                                                      kGramThreads, gram32_lds_bytes(nb)) != hipSuccess ||
+        n < 1)
+      n = 1;
+    g_split_occ[2][nb - kSplitMin] = n;
   }
   g_attr_done = true;
 }
@@ -328,7 +338,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   const bool apply = phase > 0;
   int64_t nwg = b->slots;
   const bool mixed = c.mode == 0 && b->opts.precision == 1;
-  if (c.mode == 0 && !mixed && P >= kSplitMin && P <= kSplitMax) {
+  if (c.mode == 0 && P >= kSplitMin && P <= kSplitMax && (!mixed || P > kWideMax)) {
     // apply (from pass 1 on), then the Gramian of its result
     const int idx = (int)P - kSplitMin;
     const int64_t steps = (tiles + kWaves - 1) / kWaves;
@@ -339,8 +349,13 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.part = b->part; w.part_stride = tl;
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
-    auto launch = [&](const void* k, int64_t grid, int threads, size_t lds, int kind, double bytes) {
+    auto launch = [&](const void* k, int64_t grid, int threads, size_t lds) {
       void* args[] = {&w};
+      return hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), args, lds, s) == hipSuccess;
+    };
+    // launches between one pair of profiling events (the mixed form's two
+    // Gramian variants count as one launch: one of them exits at once)
+    auto timed = [&](int kind, double bytes, auto&& enqueue) {
       ProfRec rec{};
       if (g_prof_on) {
         rec.e0 = take_event(); rec.e1 = take_event();
@@ -348,8 +363,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
         rec.call = b->call_id; rec.phase = phase; rec.real = -1;
         if (rec.e0) (void)hipEventRecord(rec.e0, s);
       }
-      if (hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), args, lds, s) != hipSuccess)
-        return false;
+      if (!enqueue()) return false;
       if (g_prof_on && rec.e0 && rec.e1) {
         (void)hipEventRecord(rec.e1, s);
         g_prof.push_back(rec);
@@ -362,18 +376,28 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       w.yout = c.y; w.ldy = c.ldy;
       w.copy_if_done = (phase == 1);
       const int64_t ga = std::max<int64_t>(1, std::min<int64_t>((int64_t)g_ncu * g_split_occ[1][idx], steps));
-      if (!launch((const void*)kSplit[idx].apply, ga, kThreads, split_lds_bytes((int)P, true), 1,
-                  16.0 * (double)b->m * (double)c.p))
+      if (!timed(1, 16.0 * (double)b->m * (double)c.p, [&] {
+            return launch((const void*)kSplit[idx].apply, ga, kThreads, split_lds_bytes((int)P, true));
+          }))
         return SQR_EHIP;
     }
-    // the Gramian of the pass's result (of the input at phase 0)
+    // the Gramian of the pass's result (of the input at phase 0); the mixed
+    // form launches the FP32 variant at phase 0 and both variants later, the
+    // one that does not match the device's choice (ctrl->gram32) exits at
+    // once.  Both fill the same nwg slots.
     w.win = apply ? c.y : c.win;
     w.ldw = apply ? c.ldy : c.ldw;
     w.copy_if_done = 0;
-    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_split_occ[0][idx]);
+    const int occ = mixed ? std::min(g_split_occ[0][idx], g_split_occ[2][idx]) : g_split_occ[0][idx];
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
     nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, steps));
-    if (!launch((const void*)kSplit[idx].gram, nwg, kGramThreads, split_lds_bytes((int)P, false), 0,
-                8.0 * (double)b->m * (double)c.p))
+    w.gram32 = (mixed && phase > 0) ? &b->ctrl->gram32 : nullptr;
+    if (!timed(0, 8.0 * (double)b->m * (double)c.p, [&] {
+          if (mixed && !launch((const void*)kSplit[idx].gram32, nwg, kGramThreads, gram32_lds_bytes((int)P)))
+            return false;
+          return (mixed && phase == 0) ||
+                 launch((const void*)kSplit[idx].gram, nwg, kGramThreads, split_lds_bytes((int)P, false));
+        }))
       return SQR_EHIP;
   } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
@@ -592,7 +616,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   sqr_default_opts(&o);
   if (opts) o = *opts;
   if (!opts_ok(o)) return SQR_EOPT;
-  if (o.precision == 1 && n > 16 * kWideMax) return SQR_EOPT;   // mixed form up to 128 columns
+  if (o.precision == 1 && n > 16 * kSplitMax) return SQR_EOPT;   // mixed form up to 256 columns
   set_kernel_attributes();
   sqr_basis* b = new sqr_basis();
   b->m = m; b->n = n; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;

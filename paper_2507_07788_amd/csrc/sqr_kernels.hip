@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sqr_device.h"
 
 namespace sqr {
@@ -580,15 +582,17 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Orth calls of 9..16 blocks (129..256 columns): the apply and the Gramian
+// Orth calls of 8..16 blocks (113..256 columns): the apply and the Gramian
 // of a pass as two launches.  Registers cannot hold a row tile of Y, the
 // prefetched input and all Gramian accumulators at once, so
 //   wide_apply<NB>: Y = W R~^{-1} with the row tile's Y blocks in registers
 //     (as in wide_pass) and the panel [C_J; D_J] of block J staged through
 //     LDS while block J-1 is formed (one barrier per block);
-//   gram_pass<NB>:  the Gramian of the m x n result (upper 16x16 blocks),
-//     eight waves, 64-row steps staged in LDS in MFMA operand order, the
-//     blocks (I, J) dealt out to the waves; also the initial Gramian of A.
+//   gram_pass<NB, G32>:  the Gramian of the m x n result (upper 16x16
+//     blocks), eight waves, 64-row steps staged in LDS in MFMA operand order,
+//     the blocks (I, J) dealt out to the waves; also the initial Gramian of A.
+//     G32 (mixed form): the Gramian of the FP32-rounded tiles on FP32 MFMA
+//     with FP32 accumulation per workgroup.
 // The pass then reads the tall data three times (W, and Y twice) instead of
 // re-reading the prefix Y_<J for every block.
 // ---------------------------------------------------------------------------
@@ -749,9 +753,11 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
   }
 }
 
-template <int NB>
+template <int NB, bool G32>
 __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
   extern __shared__ double lds[];
+  using Op = typename std::conditional<G32, float, double>::type;
+  using Acc = typename std::conditional<G32, f4, d4>::type;
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int KP = (NP + kGramWaves - 1) / kGramWaves;
   constexpr int H = (NB + 1) / 2;                 // blocks loaded per wave
@@ -765,6 +771,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
   const int64_t s0 = (int64_t)blockIdx.x * per;
   const int64_t s1 = min(steps, s0 + per);
   if (a.done && *a.done) return;
+  if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
 
   auto load_h = [&](int64_t tile, d4 (&w)[H]) {
     const int64_t row = tile * 16 + x;
@@ -785,12 +792,12 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
       }
   };
 
-  d4 acc[KP];
+  Acc acc[KP];
   int pi[KP], pj[KP];
   bool pok[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    acc[k] = Acc{0, 0, 0, 0};
     const int pidx = wave + kGramWaves * k;
     pok[k] = pidx < NP;
     int J = 0;
@@ -801,7 +808,9 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
 
   d4 wnext[H];
   load_h(min(s0 * kWaves + tw, tiles - 1), wnext);
-  double* myop = lds + tw * NB * 4 * kOpSlot;
+  // operand slots in the Gramian's precision (FP32: half the LDS)
+  Op* const ops = reinterpret_cast<Op*>(lds);
+  Op* myop = ops + tw * NB * 4 * kOpSlot;
   for (int64_t s = s0; s < s1; ++s) {
     const int64_t tile = s * kWaves + tw;
     const bool tile_ok = tile < tiles;
@@ -812,7 +821,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
       if (J < NB) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = tile_ok ? wnext[jj][r] : 0.0;
+          myop[(J * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = (Op)(tile_ok ? wnext[jj][r] : 0.0);
       }
     }
     load_h(min(tile + kWaves, tiles - 1), wnext);
@@ -820,30 +829,40 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (pok[k]) {
-        const double* oa = lds + pi[k] * 4 * kOpSlot + x + 17 * g;
-        const double* ob = lds + pj[k] * 4 * kOpSlot + x + 17 * g;
+        const Op* oa = ops + pi[k] * 4 * kOpSlot + x + 17 * g;
+        const Op* ob = ops + pj[k] * 4 * kOpSlot + x + 17 * g;
 #pragma unroll
         for (int t = 0; t < kWaves; ++t)
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+          for (int u = 0; u < 4; ++u) {
+            if constexpr (G32)
+              acc[k] = mfma32(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+            else
+              acc[k] = mfma(oa[(t * NB * 4 + u) * kOpSlot], ob[(t * NB * 4 + u) * kOpSlot], acc[k]);
+          }
       }
     }
     __syncthreads();
   }
+  // Slot: block J holds rows 0..16J+15 of Gramian columns 16J..16J+15 (the
+  // two MFMA forms place the 16x16 result differently across lanes).
   double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (pok[k]) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (G32)
+          out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + 4 * g + r) * 16 + x] = (double)acc[k][r];
+        else
+          out[e_off(0, pj[k]) + (int64_t)(16 * pi[k] + g + 4 * r) * 16 + x] = acc[k][r];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// small_step: one workgroup of 1024 threads finishes a pass.
+// small_step: one workgroup of 256 threads finishes a pass.
 // ---------------------------------------------------------------------------
 constexpr int kSmallThreads = 256;
 constexpr int kSmallWaves = kSmallThreads / 64;

@@ -271,7 +271,8 @@ def test_append_growth_parity_full_1e6():
     assert np.max(np.abs(Qg[rows, :10] - Qo[rows, :10])) <= 1e-8 * np.max(np.abs(Qo[:, :10]))
 
 
-@pytest.mark.parametrize("m,n", [(6000, 10), (6000, 16), (5000, 64), (4001, 128)])
+@pytest.mark.parametrize("m,n", [(6000, 10), (6000, 16), (5000, 64), (4001, 128), (3001, 160),
+                                 (3000, 256)])
 @pytest.mark.parametrize("kappa", [1e4, 1e8, 1e12, 1e15])
 def test_orth_mixed_parity(m, n, kappa):
     """Mixed FP32/FP64 form against the oracle's mixed form and the FP64 QR."""
@@ -288,7 +289,7 @@ def test_orth_mixed_parity(m, n, kappa):
 
 
 def test_orth_mixed_limits():
-    A = dev(S.test_matrix(1000, 130, 10.0, seed=(14,)))
+    A = dev(S.test_matrix(1000, 257, 10.0, seed=(14,)))
     with pytest.raises(RuntimeError):
         sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=1))
     with pytest.raises(RuntimeError):
@@ -369,11 +370,17 @@ def test_orth_full_size_m4e6_n128_kappa1e12(precision):
 
 @pytest.mark.slow
 def test_orth_full_size_m2e7_n256_kappa1e15():
+    """FP64, then the mixed form on the same matrix."""
     A = S.test_matrix_device(20_000_000, 256, 1e15, (3,))
-    b, info = sq.sqr_orth(A)
-    assert info["status"] == 0 and info["passes"] <= 10
-    loo, rrr = _invariants_dev(A, b.Q, b.R, 256)
-    assert loo <= 1e-12 and rrr <= 1e-13
+    for precision in (0, 1):
+        print(f"orth 2e7 x 256, precision {precision}", flush=True)
+        b, info = sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=precision))
+        assert info["status"] == 0 and info["passes"] <= 10
+        loo, rrr = _invariants_dev(A, b.Q, b.R, 256)
+        assert loo <= 1e-12 and rrr <= 1e-13
+        sq.sqr_free(b)
+        del b
+        torch.cuda.empty_cache()
 
 
 def test_orth_maximum_width_528():
