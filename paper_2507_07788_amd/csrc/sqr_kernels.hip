@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "sqr_device.h"
 
@@ -896,53 +897,148 @@ __device__ double block_sum(double v, double* buf, bool lds_only) {
 }
 
 
-// In-place upper Cholesky of the row-major p x p matrix M (right-looking).
-// Returns false on breakdown: a pivot that is not > 0 or not finite.
-__device__ bool chol_upper(double* M, int p, bool lds_only) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < p; ++j) {
-    wg_sync(lds_only);
-    const double d = M[(int64_t)j * p + j];
-    const bool bad = !(d > 0.0) || !isfinite(d);  // uniform: all read d
-    wg_sync(lds_only);  // every thread has read d before anyone returns or writes
-    if (bad) return false;
-    const double r = sqrt(d);
-    if (tid == 0) M[(int64_t)j * p + j] = r;
-    for (int k = j + 1 + tid; k < p; k += kSmallThreads) M[(int64_t)j * p + k] /= r;
-    wg_sync(lds_only);
-    // trailing update of the upper part: rows dealt to 16 thread groups,
-    // columns to the 16 threads of a group
-    for (int i = j + 1 + (tid >> 4); i < p; i += kSmallThreads / 16) {
-      const double mji = M[(int64_t)j * p + i];
-      for (int k = i + (tid & 15); k < p; k += 16) M[(int64_t)i * p + k] -= mji * M[(int64_t)j * p + k];
-    }
-  }
-  wg_sync(lds_only);
-  return true;
+// Broadcast lane l's double to the wave (l uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// The same factorisation by wave 0 alone for p <= 64 (no workgroup barriers;
-// LDS hand-offs within the wave).  Every thread receives the outcome.
-__device__ bool chol_upper_wave(double* M, int p, int* flag) {
-  const int tid = threadIdx.x;
-  wg_sync(true);
-  if (tid < 64) {
-    bool ok = true;
-    for (int j = 0; j < p; ++j) {
-      const double d = M[(int64_t)j * p + j];
-      if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }  // uniform in the wave
-      const double r = sqrt(d);
-      for (int k = j + 1 + tid; k < p; k += 64) M[(int64_t)j * p + k] /= r;
-      wave_lds_sync();
-      if (tid == 0) M[(int64_t)j * p + j] = r;
-      const int w = p - j - 1;
-      for (int e = tid; e < w * w; e += 64) {
-        const int i = j + 1 + e / w, k = j + 1 + e % w;
-        if (k >= i) M[(int64_t)i * p + k] -= M[(int64_t)j * p + i] * M[(int64_t)j * p + k];
+// Lane L of each row of 16 lanes to the whole row (DPP row_newbcast), in
+// vector registers.
+template <int L>
+__device__ __forceinline__ double row_bcast(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x150 + L, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x150 + L, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The same double in every lane, as a wave-uniform (scalar) value.
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Row I of the 16x16 wave factorisation below (branch-free apart from the
+// uniform tests): pivot check, scaling of row I, and M_lk -= R_Il R_Ik for
+// every later row l, R_Il broadcast from lane l.  Entries below the
+// diagonal of lane k's column (rows l > k) are updated too and never read.
+template <int I, int L>
+__device__ __forceinline__ void chol16_update(double (&col)[16]) {
+  if constexpr (L > I) col[L] -= row_bcast<L>(col[I]) * col[I];
+}
+template <int I, int... L>
+__device__ __forceinline__ void chol16_row(double (&col)[16], int k, int nb, bool& ok,
+                                           std::integer_sequence<int, L...>) {
+  if (!ok || I >= nb) return;   // uniform
+  const double d = uniform_d(row_bcast<I>(col[I]));
+  if (!(d > 0.0) || !isfinite(d)) {
+    ok = false;
+    return;
+  }
+  const double r = sqrt(d);
+  const double q = col[I] / r;
+  col[I] = (k == I) ? r : ((k > I) ? q : col[I]);
+  (chol16_update<I, L>(col), ...);
+}
+template <int... I>
+__device__ __forceinline__ bool chol16_rows(double (&col)[16], int k, int nb,
+                                            std::integer_sequence<int, I...> seq) {
+  bool ok = true;
+  (chol16_row<I>(col, k, nb, ok, seq), ...);
+  return ok;
+}
+
+// Column k of R^{-1} (R the factor above, identity beyond nb) by back
+// substitution, row I = 15 .. 0: t_I = (e_k[I] - sum_{L > I} R_IL t_L) / R_II
+// with R_IL broadcast from lane L (zero beyond nb, where t_I = e_k[I]).
+template <int I, int L>
+__device__ __forceinline__ void inv16_term(const double (&col)[16], const double (&t)[16], double& s) {
+  if constexpr (L > I) s -= row_bcast<L>(col[I]) * t[L];
+}
+template <int J, int... L>
+__device__ __forceinline__ void inv16_row(const double (&col)[16], double (&t)[16], int k, int nb,
+                                          std::integer_sequence<int, L...>) {
+  constexpr int I = 15 - J;
+  double s = (k == I) ? 1.0 : 0.0;
+  if (I < nb) {   // uniform
+    (inv16_term<I, L>(col, t, s), ...);
+    s = s / row_bcast<I>(col[I]);
+  }
+  t[I] = s;
+}
+template <int... J>
+__device__ __forceinline__ void inv16_rows(const double (&col)[16], double (&t)[16], int k, int nb,
+                                           std::integer_sequence<int, J...> seq) {
+  (inv16_row<J>(col, t, k, nb, seq), ...);
+}
+
+// In-place upper Cholesky (right-looking) of the nb x nb block at B
+// (row-major, pitch ld, nb <= 16) by one wave, in vector registers: every
+// row of 16 lanes holds the block, lane k column k; for each row i the pivot
+// is checked, row i is scaled (r on the diagonal, the rest divided by r) and
+// every later row l takes M_lk -= R_il R_ik, with R_il broadcast from lane l
+// by DPP.  Breakdown: a pivot that is not > 0 or not finite (B untouched).
+// On success the factor is written back to B and, if given, to copy16
+// (pitch 16), and dinv (if given) receives the 16 x 16 inverse of the factor
+// padded with the identity beyond nb (row-major).  Padding lanes and rows
+// (>= nb) of the factor hold zeros and stay zero.
+__device__ __noinline__ bool chol16_wave(double* B, int ld, int nb_in, double* copy16, double* dinv) {
+  const int nb = __builtin_amdgcn_readfirstlane(nb_in);
+  const int ln = threadIdx.x & 63;
+  const int k = ln & 15;
+  double col[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) col[i] = (i < nb && k < nb && i <= k) ? B[i * ld + k] : 0.0;
+  const bool ok = chol16_rows(col, k, nb, std::make_integer_sequence<int, 16>{});
+  if (ok && ln < nb) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i <= ln && i < nb) {
+        B[i * ld + ln] = col[i];
+        if (copy16) copy16[i * 16 + ln] = col[i];
       }
-      wave_lds_sync();
     }
-    if (tid == 0) *flag = ok ? 1 : 0;
+  }
+  if (ok && dinv) {
+    double t[16];
+    inv16_rows(col, t, k, nb, std::make_integer_sequence<int, 16>{});
+    if (ln < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dinv[i * 16 + ln] = t[i];
+    }
+  }
+  return ok;
+}
+
+// dinv = inverse of the nb x nb upper triangular block at B (row-major,
+// pitch ld), padded with the identity to 16 x 16 (row-major), by one wave.
+__device__ __noinline__ void inv16_wave(const double* B, int ld, int nb_in, double* dinv) {
+  const int nb = __builtin_amdgcn_readfirstlane(nb_in);
+  const int ln = threadIdx.x & 63;
+  const int k = ln & 15;
+  double col[16], t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) col[i] = (i < nb && k < nb && i <= k) ? B[i * ld + k] : 0.0;
+  inv16_rows(col, t, k, nb, std::make_integer_sequence<int, 16>{});
+  if (ln < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dinv[i * 16 + ln] = t[i];
+  }
+}
+
+// Upper Cholesky of the p x p matrix M (p <= 16, in LDS) by wave 0; every
+// thread receives the outcome.
+__device__ bool chol_upper_wave(double* M, int p, int* flag, double* dinv) {
+  wg_sync(true);
+  if (threadIdx.x < 64) {
+    const bool ok = chol16_wave(M, p, p, nullptr, dinv);
+    if (threadIdx.x == 0) *flag = ok ? 1 : 0;
   }
   wg_sync(true);
   return *flag != 0;
@@ -982,34 +1078,61 @@ __device__ __forceinline__ void fill_rows(double* dst, int rows, int cols, F f) 
   }
 }
 
-// Blocked right-looking form of the same factorisation for p > 16: the 16
-// rows of band K are factored column by column (the band's rows against all
-// columns to their right), then every trailing block (I, J), K < I <= J, is
-// updated as M_IJ -= R_KI^T R_KJ on MFMA.  Breakdown is decided on the
-// pivot as it stands after all earlier updates, as in the unblocked form.
-__device__ bool chol_blocked(double* M, int p, bool lds_only) {
+// In-place upper Cholesky (right-looking) of the row-major p x p matrix M
+// for p > 16, band by band of 16 rows:
+//   (a) one wave factors the diagonal block M_KK (as it stands after all
+//       earlier updates) in registers (chol16_wave) and copies the factor to
+//       `blk`; breakdown, a pivot that is not > 0 or not finite, is decided
+//       on each pivot in turn;
+//   (b) the band's panel R_K,>K = R_KK^{-T} M_K,>K by forward substitution,
+//       one column per thread (the operations a column-by-column
+//       factorisation applies to those entries, in the same order);
+//   (c) every trailing block (I, J), K < I <= J, is updated as
+//       M_IJ -= R_KI^T R_KJ on MFMA.
+// Three workgroup barriers per band.  M is in LDS or in global memory; blk
+// holds 256 doubles of LDS.  Returns false on breakdown; on success dinv
+// (global memory) receives the inverses of the 16 x 16 diagonal blocks,
+// padded with the identity (row-major, 256 doubles per block).
+__device__ bool chol_blocked(double* M, int p, bool lds_only, double* blk, int* flag, double* dinv) {
   const int tid = threadIdx.x;
   const int wv = tid >> 6, ln = tid & 63, x = ln & 15, g = ln >> 4;
   const int nbk = (p + 15) >> 4;
   for (int K = 0; K < nbk; ++K) {
-    const int b0 = 16 * K, b1 = min(p, b0 + 16);
-    for (int j = b0; j < b1; ++j) {
-      wg_sync(lds_only);
-      const double d = M[(int64_t)j * p + j];
-      if (!(d > 0.0) || !isfinite(d)) {   // uniform: all read d
-        wg_sync(lds_only);                // before the caller rewrites M
-        return false;
-      }
-      const double r = sqrt(d);
-      for (int c = j + 1 + tid; c < p; c += kSmallThreads) M[(int64_t)j * p + c] /= r;
-      wg_sync(lds_only);
-      if (tid == 0) M[(int64_t)j * p + j] = r;
-      for (int i = j + 1 + (tid >> 4); i < b1; i += kSmallThreads / 16) {
-        const double mji = M[(int64_t)j * p + i];
-        for (int c = i + (tid & 15); c < p; c += 16) M[(int64_t)i * p + c] -= mji * M[(int64_t)j * p + c];
-      }
+    const int b0 = 16 * K, b1 = min(p, b0 + 16), nb = b1 - b0;
+    wg_sync(lds_only);   // the trailing update of band K-1 is complete
+    if (wv == 0) {
+      // (a) diagonal block by one wave, also copied to blk for the panel
+      const bool ok = chol16_wave(M + (int64_t)b0 * p + b0, p, nb, blk, nullptr);
+      if (ln == 0) *flag = ok ? 1 : 0;
     }
     wg_sync(lds_only);
+    if (!*flag) {
+      wg_sync(lds_only);   // every thread has read the flag before it is reused
+      return false;
+    }
+    // (b) panel rows b0..b1-1, columns b1..p-1
+    for (int c = b1 + tid; c < p; c += kSmallThreads) {
+      // keep the reads of blk inside the loop (hoisted, its 136 entries
+      // would not fit in registers)
+      __asm__ volatile("" ::: "memory");
+      double xc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xc[i] = (i < nb) ? M[(int64_t)(b0 + i) * p + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (i < nb) {
+          double s = xc[i];
+#pragma unroll
+          for (int k = 0; k < i; ++k) s -= blk[k * 16 + i] * xc[k];
+          xc[i] = s / blk[i * 16 + i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < nb) M[(int64_t)(b0 + i) * p + c] = xc[i];
+    }
+    wg_sync(lds_only);
+    // (c) trailing blocks, one 16x16 tile per wave at a time
     const int rem = nbk - K - 1;
     for (int t = wv; t < rem * (rem + 1) / 2; t += kSmallWaves) {
       int Jr = 0;
@@ -1037,6 +1160,9 @@ __device__ bool chol_blocked(double* M, int p, bool lds_only) {
     }
   }
   wg_sync(lds_only);
+  // inverses of the diagonal blocks, one block per wave at a time
+  for (int K = wv; K < nbk; K += kSmallWaves)
+    inv16_wave(M + (int64_t)(16 * K) * p + 16 * K, p, min(16, p - 16 * K), dinv + 256 * K);
   return true;
 }
 
@@ -1136,14 +1262,14 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   fill_rows(Bt, q, p, [&](int i, int j) {
     return E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
   });
-  // old diagonal block of R (the identity at phase 0, Algorithms 1 and 2) and
-  // old B (zero at phase 0), loaded together with the Gramian blocks
+  // old diagonal block of R and old B, loaded together with the Gramian
+  // blocks (at phase 0 they are the identity and zero: step 6 then copies)
   const bool ph0 = a.phase == 0;
-  fill_rows(Ro, p, p, [&](int i, int j) {
-    return ph0 ? (i == j ? 1.0 : 0.0) : R[roff + i + (int64_t)j * ldr];
-  });
-  if (a.mode == 1)
-    fill_rows(Bo, q, p, [&](int i, int j) { return ph0 ? 0.0 : R[i + (int64_t)(q + j) * ldr]; });
+  if (!ph0) {
+    fill_rows(Ro, p, p, [&](int i, int j) { return R[roff + i + (int64_t)j * ldr]; });
+    if (a.mode == 1)
+      fill_rows(Bo, q, p, [&](int i, int j) { return R[i + (int64_t)(q + j) * ldr]; });
+  }
   // phase 0: the stores of R above precede the stores of step 6 by other threads
   wg_sync(lo && a.phase > 0);
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
@@ -1211,88 +1337,211 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     return;
   }
   const int pass = a.phase + 1;
-  // 5. Shift decision and factorisation.
-  bool shifted = (a.mode == 0 && pass == 1 && a.first_pass_shift);
-  int attempts = 0;
+  // 5. Shift decision and factorisation: an unshifted attempt (except on a
+  //    shifted first pass), and after its breakdown, or on a shifted first
+  //    pass, the shift from ||X||_2 with x10 escalation.  One factorisation
+  //    site for all attempts.
+  bool shifted = false;
+  bool need_shift = (a.mode == 0 && pass == 1 && a.first_pass_shift);
+  int attempts = 0, esc = 0;
   double sigma = 0.0;
+  // FP32 Gramian (mixed form): sigma = p u32 ||X||, floor 2 u32
+  constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+  const double ufl = cur32 ? kU32 : a.u;
   bool ok = false;
-  if (!shifted) {
-    fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
+  for (;;) {
+    if (need_shift) {
+      need_shift = false;
+      shifted = true;
+      // ||X||_2 by power iteration from the all-ones vector (on a copy of X in
+      // LDS when only M lives there: M is rebuilt from X below).
+      const double* Xs = X;
+      if (a.lds_matrices == 2) {
+        fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
+        Xs = M;
+      }
+      // X is symmetric (mirrored from its upper triangle), so (X v)_i is read
+      // along column i: X[j p + i] over j, coalesced across rows i.
+      double lam = 0.0;
+      if (p <= 16) {
+        // One wave, in registers: X (zero-padded to 16 x 16) is held in the
+        // MFMA result layout, reg r of lane (x, g) = X[g + 4r][x].  X is
+        // symmetric, so that layout is also the A and B operand layout of a
+        // product with X: X^2 is four MFMAs on the registers, and so are
+        // X^4, X^8, ...  The steps of the iteration are applied as
+        // v = X^s 1 / ||X^s 1|| with X^s the product of the powers X^(2^k)
+        // for the set bits k of s (each power scaled to unit Frobenius norm;
+        // scaling only changes the length of the iterate), the same vector as
+        // s normalised steps.  The vector is kept as column 0 of a 16 x 16
+        // operand, which the MFMA result layout also matches.
+        if (tid < 64) {
+          const int x = tid & 15, g = tid >> 4;
+          auto wsum = [](double t) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            return t;
+          };
+          auto fro = [&](const d4& t) {
+            return sqrt(wsum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3]));
+          };
+          auto prod = [&](const d4& pa, const d4& pb) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = mfma(pa[r], pb[r], acc);
+            return acc;
+          };
+          d4 xm;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            xm[r] = (g + 4 * r < p && x < p) ? Xs[(int64_t)(g + 4 * r) * p + x] : 0.0;
+          d4 vv;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) vv[r] = (x == 0 && g + 4 * r < p) ? 1.0 : 0.0;
+          const double f = fro(xm);
+          double lw;
+          if (!(f > 0.0) || !isfinite(f)) {
+            lw = isfinite(f) ? 0.0 : __builtin_nan("");
+          } else {
+            d4 pw = xm * (1.0 / f);   // X^(2^k), scaled
+            for (int k = 0; (a.power_steps >> k) != 0; ++k) {
+              if ((a.power_steps >> k) & 1) vv = prod(pw, vv);
+              if ((a.power_steps >> (k + 1)) != 0) {
+                pw = prod(pw, pw);
+                const double fp = fro(pw);
+                pw = pw * (1.0 / fp);
+              }
+            }
+            const double nrm = fro(vv);
+            if (!(nrm > 0.0) || !isfinite(nrm)) {
+              lw = isfinite(nrm) ? 0.0 : __builtin_nan("");
+            } else {
+              vv = vv * (1.0 / nrm);
+              const d4 xv = prod(xm, vv);
+              lw = fabs(wsum(vv[0] * xv[0] + vv[1] * xv[1] + vv[2] * xv[2] + vv[3] * xv[3]));
+            }
+          }
+          if (tid == 0) w[0] = lw;
+        }
+        wg_sync(lo);
+        lam = w[0];
+      } else if (p <= 64) {
+        // one wave, lane i = row i, v_i in a register and v_j broadcast by
+        // readlane: no workgroup barriers in the iteration
+        if (tid < 64) {
+          const bool act = tid < p;
+          const int i = act ? tid : 0;
+          double vi = act ? 1.0 / sqrt((double)p) : 0.0;
+          double lw = 0.0;
+          bool early = false;
+          auto mv = [&]() {
+            double t = 0.0;
+  #pragma unroll 8
+            for (int j = 0; j < p; ++j) t += Xs[(int64_t)j * p + i] * readlane_d(vi, j);
+            return act ? t : 0.0;
+          };
+          auto wsum = [](double x) {
+  #pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+            return x;
+          };
+          for (int s = 0; s < a.power_steps; ++s) {
+            const double t = mv();
+            const double nrm = sqrt(wsum(t * t));
+            if (!(nrm > 0.0) || !isfinite(nrm)) {
+              lw = isfinite(nrm) ? nrm : __builtin_nan("");
+              early = true;
+              break;
+            }
+            vi = t / nrm;
+          }
+          if (!early) lw = fabs(wsum(vi * mv()));
+          if (tid == 0) w[0] = lw;
+        }
+        wg_sync(lo);
+        lam = w[0];
+      } else {
+        // all waves: thread t takes row t mod p and one of H column ranges;
+        // the H partial sums of a row are added in range order
+        const int H = max(1, kSmallThreads / p);
+        for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
+        wg_sync(lo);
+        // returns w_i (thread i < p, else 0) with the partial sums in w[]
+        auto mv = [&]() {
+          for (int t0 = tid; t0 < p * H; t0 += kSmallThreads) {
+            const int i = t0 % p, h = t0 / p;
+            const int j0 = h * p / H, j1 = (h + 1) * p / H;
+            double t = 0.0;
+  #pragma unroll 16
+            for (int j = j0; j < j1; ++j) t += Xs[(int64_t)j * p + i] * v[j];
+            w[h * p + i] = t;
+          }
+          wg_sync(lo);
+          double t = 0.0;
+          if (tid < p)
+            for (int h = 0; h < H; ++h) t += w[h * p + tid];
+          return t;
+        };
+        bool early = false;
+        for (int s = 0; s < a.power_steps; ++s) {
+          const double t = mv();
+          const double nrm = sqrt(block_sum(t * t, red, lo));
+          if (!(nrm > 0.0) || !isfinite(nrm)) {
+            lam = isfinite(nrm) ? nrm : __builtin_nan("");
+            early = true;
+            break;
+          }
+          if (tid < p) v[tid] = t / nrm;
+          wg_sync(lo);
+        }
+        if (!early) {
+          const double t = mv();
+          lam = fabs(block_sum(tid < p ? v[tid] * t : 0.0, red, lo));
+        }
+      }
+      const double mm = (double)a.m;
+      const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
+                                       : (mm * q + (double)q * (q + 1));
+      sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
+                    : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
+    }
+    fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
     ++attempts;
-    ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_blocked(M, p, mlo);
-    shifted = !ok;
+    ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag, a.rinv) : chol_blocked(M, p, mlo, vw, &cflag, a.rinv);
+    if (ok) break;
+    if (!shifted) {
+      need_shift = true;
+      continue;
+    }
+    if (esc >= a.max_escalations) break;
+    ++esc;
+    sigma = fmax(10.0 * sigma, 2.0 * ufl);
   }
-  if (shifted) {
-    // ||X||_2 by power iteration from the all-ones vector (on a copy of X in
-    // LDS when only M lives there: M is rebuilt from X below).
-    const double* Xs = X;
-    if (a.lds_matrices == 2) {
-      fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
-      Xs = M;
+  if (!ok) {
+    if (tid == 0) {
+      c->status = 2;  // SQR_BREAKDOWN
+      c->chol_attempts = prev_att + attempts;
+      c->orth_fro = err;
+      c->done = 1;
+      publish(a, Outcome{1, 2, 0, -1, prev_att + attempts, -1, 0.0, err});
     }
-    for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
-    wg_sync(lo);
-    double lam = 0.0;
-    bool early = false;
-    for (int s = 0; s < a.power_steps; ++s) {
-      double pp2 = 0.0;
-      for (int i = tid; i < p; i += kSmallThreads) {
-        double t = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < p; ++j) t += Xs[(int64_t)i * p + j] * v[j];
-        w[i] = t;
-        pp2 += t * t;
-      }
-      const double nrm = sqrt(block_sum(pp2, red, lo));
-      if (!(nrm > 0.0) || !isfinite(nrm)) {
-        lam = isfinite(nrm) ? nrm : __builtin_nan("");
-        early = true;
-        break;
-      }
-      for (int i = tid; i < p; i += kSmallThreads) v[i] = w[i] / nrm;
-      wg_sync(lo);
-    }
-    if (!early) {
-      double pp2 = 0.0;
-      for (int i = tid; i < p; i += kSmallThreads) {
-        double t = 0.0;
-        for (int j = 0; j < p; ++j) t += Xs[(int64_t)i * p + j] * v[j];
-        pp2 += v[i] * t;
-      }
-      lam = fabs(block_sum(pp2, red, lo));
-    }
-    const double mm = (double)a.m;
-    const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
-                                     : (mm * q + (double)q * (q + 1));
-    // FP32 Gramian (mixed form): sigma = p u32 ||X||, floor 2 u32
-    constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
-    const double ufl = cur32 ? kU32 : a.u;
-    sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
-                  : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
-    for (int esc = 0;; ++esc) {
-      fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
-      ++attempts;
-      ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag) : chol_blocked(M, p, mlo);
-      if (ok) break;
-      if (esc >= a.max_escalations) break;
-      sigma = fmax(10.0 * sigma, 2.0 * ufl);
-    }
-    if (!ok) {
-      if (tid == 0) {
-        c->status = 2;  // SQR_BREAKDOWN
-        c->chol_attempts = prev_att + attempts;
-        c->orth_fro = err;
-        c->done = 1;
-        publish(a, Outcome{1, 2, 0, -1, prev_att + attempts, -1, 0.0, err});
-      }
-      return;
-    }
+    return;
   }
   wg_sync(lo);
   // 6. B <- B + B~ R_old, then R <- R~ R_old (Algorithm 2; Algorithm 1).
+  //    At phase 0 (R_old = I, B_old = 0) both are copies.
   //    Fixed trip counts for p <= 16 (one row of B per thread, the row of
   //    B~ in registers; stores along columns of R coalesce).
-  if (a.mode == 1 && q > 0) {
+  if (ph0) {
+    if (a.mode == 1)
+      for (int e = tid; e < qp; e += kSmallThreads) {
+        const int i = e / p, j = e % p;
+        R[i + (int64_t)(q + j) * ldr] = Bt[e];
+      }
+    for (int e = tid; e < pp; e += kSmallThreads) {
+      const int i = e % p, j = e / p;
+      R[roff + i + (int64_t)j * ldr] = (i <= j) ? M[(int64_t)i * p + j] : 0.0;
+    }
+  } else if (a.mode == 1 && q > 0) {
     if (p <= 16) {
       for (int i = tid; i < q; i += kSmallThreads) {
         double br[16];
@@ -1318,7 +1567,8 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       }
     }
   }
-  if (p <= 16) {
+  if (ph0) {
+  } else if (p <= 16) {
     for (int e = tid; e < pp; e += kSmallThreads) {
       const int i = e / p, j = e % p;
       double s = 0.0;
@@ -1363,40 +1613,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       if ((i >> 4) > (j >> 4)) R[roff + i + (int64_t)j * ldr] = 0.0;
     }
   }
-  // 7. Operands of the next pass.  D_J = inverse of the diagonal block J of
-  //    R~ (identity beyond p), by back substitution on each column.
-  //    Fixed trip counts (masked beyond column cc) let every load of the
-  //    block issue ahead of the dependent arithmetic.
-  for (int t = tid; t < a.nblk * 16; t += kSmallThreads) {
-    const int J = t >> 4, cc = t & 15, b0 = 16 * J;
-    const int pb = min(16, p - b0);
-    double col[16];
-    if (cc >= pb) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) col[i] = (i == cc) ? 1.0 : 0.0;
-    } else {
-      const double* Mb = M + (int64_t)b0 * p + b0;
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        double s = (i == cc) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = i + 1; k < 16; ++k)
-          if (k <= cc) s -= Mb[(int64_t)i * p + k] * col[k];
-        if (i <= cc)
-          col[i] = s / Mb[(int64_t)i * p + i];
-        else
-          col[i] = 0.0;
-      }
-    }
-    double* rv = a.rinv + J * 256;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) rv[i * 16 + cc] = col[i];
-    if (a.nblk <= kLdsDBlocks) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) vw[J * 256 + i * 16 + cc] = col[i];
-    }
-  }
-  // D_J complete (in LDS, or in global memory beyond kLdsDBlocks blocks)
+  // 7. Operands of the next pass.  D_J, the inverse of the diagonal block J
+  //    of R~ (identity beyond p), was stored with the factorisation (wave 0,
+  //    global memory); the C_J below read it from LDS when it fits.
+  wg_sync(false);
+  if (a.nblk <= kLdsDBlocks)
+    for (int e = tid; e < a.nblk * 256; e += kSmallThreads) vw[e] = a.rinv[e];
   wg_sync(a.nblk <= kLdsDBlocks);
   //    C_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]] D_J, so the
   //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
