@@ -1360,6 +1360,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
         fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
         Xs = M;
       }
+      wg_sync(lo);   // X (or its copy) is complete before any wave reads it
       // X is symmetric (mirrored from its upper triangle), so (X v)_i is read
       // along column i: X[j p + i] over j, coalesced across rows i.
       double lam = 0.0;
@@ -1425,40 +1426,109 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
         wg_sync(lo);
         lam = w[0];
       } else if (p <= 64) {
-        // one wave, lane i = row i, v_i in a register and v_j broadcast by
-        // readlane: no workgroup barriers in the iteration
-        if (tid < 64) {
-          const bool act = tid < p;
-          const int i = act ? tid : 0;
-          double vi = act ? 1.0 / sqrt((double)p) : 0.0;
-          double lw = 0.0;
-          bool early = false;
-          auto mv = [&]() {
-            double t = 0.0;
-  #pragma unroll 8
-            for (int j = 0; j < p; ++j) t += Xs[(int64_t)j * p + i] * readlane_d(vi, j);
-            return act ? t : 0.0;
-          };
-          auto wsum = [](double x) {
-  #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-            return x;
-          };
-          for (int s = 0; s < a.power_steps; ++s) {
-            const double t = mv();
-            const double nrm = sqrt(wsum(t * t));
-            if (!(nrm > 0.0) || !isfinite(nrm)) {
-              lw = isfinite(nrm) ? nrm : __builtin_nan("");
-              early = true;
-              break;
-            }
-            vi = t / nrm;
+        // Four waves, the same power scheme on 16 x 16 tiles (nt x nt of
+        // them, zero-padded): each power X^(2^k) is formed on MFMA from the
+        // previous one (read along columns, which symmetry allows), scaled
+        // to unit Frobenius norm and stored row-major in M; the iterate
+        // (column 0 of a 16 nt x 16 operand, in v) is multiplied by each
+        // power whose bit is set as soon as it is formed (powers of X
+        // commute).  X itself stays intact for the final Rayleigh quotient.
+        const int nt = (p + 15) >> 4;
+        const int wv = tid >> 6, x = tid & 15, g = (tid >> 4) & 3;
+        const double* src = Xs;   // the current power (X first)
+        auto opnd = [&](const double* P, int r, int c) {   // P[r][c], zero padding
+          return (r < p && c < p) ? P[(int64_t)r * p + c] : 0.0;
+        };
+        // v <- P v for the current power P (tile row I = wave), in place
+        auto apply_v = [&](const double* P) {
+          d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+          if (wv < nt) {
+            for (int K = 0; K < nt; ++K)
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int kk = 16 * K + 4 * s4 + g;
+                const double av = opnd(P, kk, 16 * wv + x);            // P[16wv + x][kk]
+                const double bv = (x == 0 && kk < p) ? v[kk] : 0.0;
+                acc = mfma(av, bv, acc);
+              }
           }
-          if (!early) lw = fabs(wsum(vi * mv()));
-          if (tid == 0) w[0] = lw;
+          wg_sync(lo);   // every wave has read v
+          if (wv < nt && x == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * wv + g + 4 * r;
+              if (row < p) v[row] = acc[r];
+            }
+          }
+          wg_sync(lo);
+        };
+        for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0;
+        // ||X||_F first: scaling only changes lengths
+        double part = 0.0;
+        for (int e = tid; e < p * p; e += kSmallThreads) part += Xs[e] * Xs[e];
+        const double f = sqrt(block_sum(part, red, lo));
+        if (!(f > 0.0) || !isfinite(f)) {
+          lam = isfinite(f) ? 0.0 : __builtin_nan("");
+        } else {
+          double scale = 1.0 / f;   // the current power is scale * src
+          for (int k = 0; (a.power_steps >> k) != 0; ++k) {
+            if ((a.power_steps >> k) & 1) apply_v(src);
+            if ((a.power_steps >> (k + 1)) == 0) break;
+            // next power: (scale src)^2, tiles t = wv, wv + 4, ...
+            d4 nxt[4];
+            double sq = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              nxt[u] = d4{0.0, 0.0, 0.0, 0.0};
+              const int t = wv + kSmallWaves * u;
+              if (t < nt * nt) {
+                const int I = t / nt, J = t % nt;
+                for (int K = 0; K < nt; ++K)
+#pragma unroll
+                  for (int s4 = 0; s4 < 4; ++s4) {
+                    const int kk = 16 * K + 4 * s4 + g;
+                    nxt[u] = mfma(opnd(src, kk, 16 * I + x) * scale, opnd(src, kk, 16 * J + x) * scale, nxt[u]);
+                  }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sq += nxt[u][r] * nxt[u][r];
+              }
+            }
+            const double fp = sqrt(block_sum(sq, red, lo));   // also: all reads of src done
+            scale = 1.0 / fp;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int t = wv + kSmallWaves * u;
+              if (t < nt * nt) {
+                const int I = t / nt, J = t % nt;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int row = 16 * I + g + 4 * r, col = 16 * J + x;
+                  if (row < p && col < p) M[(int64_t)row * p + col] = nxt[u][r];
+                }
+              }
+            }
+            src = M;
+            wg_sync(lo);
+          }
+          // lam = |v^T X v| / (v^T v) with X itself (not a copy that the
+          // powers may have overwritten)
+          double vv = 0.0;
+          for (int i = tid; i < p; i += kSmallThreads) vv += v[i] * v[i];
+          const double nv = sqrt(block_sum(vv, red, lo));
+          if (!(nv > 0.0) || !isfinite(nv)) {
+            lam = isfinite(nv) ? 0.0 : __builtin_nan("");
+          } else {
+            for (int i = tid; i < p; i += kSmallThreads) w[i] = v[i] / nv;
+            wg_sync(lo);
+            double rq = 0.0;
+            for (int i = tid; i < p; i += kSmallThreads) {
+              double t = 0.0;
+              for (int j = 0; j < p; ++j) t += X[(int64_t)j * p + i] * w[j];
+              rq += w[i] * t;
+            }
+            lam = fabs(block_sum(rq, red, lo));
+          }
         }
-        wg_sync(lo);
-        lam = w[0];
       } else {
         // all waves: thread t takes row t mod p and one of H column ranges;
         // the H partial sums of a row are added in range order

@@ -236,6 +236,31 @@ def test_append_parity_shapes(q, p):
     _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e5)
 
 
+@pytest.mark.parametrize("q,p,eps", [(500, 16, 1e-10), (500, 10, 1e-9), (300, 40, 1e-10), (90, 60, 1e-10)])
+def test_append_nearly_dependent_shifts(q, p, eps):
+    """A block almost inside the basis span: the unshifted factorisation of
+    the Schur complement breaks down, so the shift (power iteration on X) and
+    its x10 escalation run; with this q only the factor fits in LDS."""
+    m = 3001
+    A1 = S.test_matrix(m, q, 1e3, seed=(50,))
+    Q1, R1, _ = O.orth(A1)
+    rng = np.random.default_rng(51)
+    W = Q1 @ rng.standard_normal((q, p)) + eps * rng.standard_normal((m, p))
+    Qo, Ro, io = O.append(Q1, R1, W)
+    assert io["status"] == 0 and io["chol_attempts"] > io["passes"]
+    b, info = sq.sqr_orth(dev(A1), cap=q + p)
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == 0 and b.n == q + p
+    assert abs(info["passes"] - io["passes"]) <= 1
+    assert abs(info["chol_attempts"] - io["chol_attempts"]) <= 1
+    assert abs(info["sigma"][0] - io["sigma"][0]) <= 1e-2 * io["sigma"][0]
+    A = np.concatenate([A1, W], axis=1)
+    Qg, Rg = host(b.q()), host(b.r())
+    assert O.loo(Qg) <= 1e-12 and O.rrr(A, Qg, Rg) <= 1e-13
+    Bo, Bg = Ro[:q, q:], Rg[:q, q:]
+    assert np.linalg.norm(Bg - Bo) <= 1e-8 * np.linalg.norm(Bo)
+
+
 def test_append_lucky_breakdown_keeps_width():
     m, q, p = 256, 10, 3
     H = S.hadamard(m)
