@@ -1370,10 +1370,11 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
         // symmetric, so that layout is also the A and B operand layout of a
         // product with X: X^2 is four MFMAs on the registers, and so are
         // X^4, X^8, ...  The steps of the iteration are applied as
-        // v = X^s 1 / ||X^s 1|| with X^s the product of the powers X^(2^k)
-        // for the set bits k of s (each power scaled to unit Frobenius norm;
-        // scaling only changes the length of the iterate), the same vector as
-        // s normalised steps.  The vector is kept as column 0 of a 16 x 16
+        // v = X^s 1 / ||X^s 1||: the first step X 1 explicitly (X 1 = 0 ends
+        // the iteration, as in the step-by-step form), then X^(s-1) as the
+        // product of the powers X^(2^k) for the set bits k of s - 1 (each
+        // power scaled to unit Frobenius norm; scaling only changes the
+        // length of the iterate): the same vector as s normalised steps.  The vector is kept as column 0 of a 16 x 16
         // operand, which the MFMA result layout also matches.
         if (tid < 64) {
           const int x = tid & 15, g = tid >> 4;
@@ -1398,15 +1399,19 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
           d4 vv;
 #pragma unroll
           for (int r = 0; r < 4; ++r) vv[r] = (x == 0 && g + 4 * r < p) ? 1.0 : 0.0;
-          const double f = fro(xm);
+          // the first step explicitly: X 1 = 0 ends the iteration with 0
+          vv = prod(xm, vv);
+          const double n1 = fro(vv);
           double lw;
-          if (!(f > 0.0) || !isfinite(f)) {
-            lw = isfinite(f) ? 0.0 : __builtin_nan("");
+          if (!(n1 > 0.0) || !isfinite(n1)) {
+            lw = isfinite(n1) ? 0.0 : __builtin_nan("");
           } else {
-            d4 pw = xm * (1.0 / f);   // X^(2^k), scaled
-            for (int k = 0; (a.power_steps >> k) != 0; ++k) {
-              if ((a.power_steps >> k) & 1) vv = prod(pw, vv);
-              if ((a.power_steps >> (k + 1)) != 0) {
+            vv = vv * (1.0 / n1);
+            const int rest = a.power_steps - 1;
+            d4 pw = xm * (1.0 / fro(xm));   // X^(2^k), scaled
+            for (int k = 0; (rest >> k) != 0; ++k) {
+              if ((rest >> k) & 1) vv = prod(pw, vv);
+              if ((rest >> (k + 1)) != 0) {
                 pw = prod(pw, pw);
                 const double fp = fro(pw);
                 pw = pw * (1.0 / fp);
@@ -1430,9 +1435,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
         // them, zero-padded): each power X^(2^k) is formed on MFMA from the
         // previous one (read along columns, which symmetry allows), scaled
         // to unit Frobenius norm and stored row-major in M; the iterate
-        // (column 0 of a 16 nt x 16 operand, in v) is multiplied by each
-        // power whose bit is set as soon as it is formed (powers of X
-        // commute).  X itself stays intact for the final Rayleigh quotient.
+        // (column 0 of a 16 nt x 16 operand, in v), after the explicit first
+        // step X 1, is multiplied by each power whose bit of s - 1 is set as
+        // soon as it is formed (powers of X commute).  X itself stays intact
+        // for the final Rayleigh quotient.
         const int nt = (p + 15) >> 4;
         const int wv = tid >> 6, x = tid & 15, g = (tid >> 4) & 3;
         const double* src = Xs;   // the current power (X first)
@@ -1463,17 +1469,25 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
           wg_sync(lo);
         };
         for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0;
-        // ||X||_F first: scaling only changes lengths
+        // ||X||_F (scaling only changes lengths)
         double part = 0.0;
         for (int e = tid; e < p * p; e += kSmallThreads) part += Xs[e] * Xs[e];
         const double f = sqrt(block_sum(part, red, lo));
-        if (!(f > 0.0) || !isfinite(f)) {
-          lam = isfinite(f) ? 0.0 : __builtin_nan("");
+        // the first step explicitly: X 1 = 0 ends the iteration with 0
+        apply_v(src);
+        double n1 = 0.0;
+        for (int i = tid; i < p; i += kSmallThreads) n1 += v[i] * v[i];
+        n1 = sqrt(block_sum(n1, red, lo));
+        if (!(n1 > 0.0) || !isfinite(n1) || !isfinite(f)) {
+          lam = (isfinite(n1) && isfinite(f)) ? 0.0 : __builtin_nan("");
         } else {
+          for (int i = tid; i < p; i += kSmallThreads) v[i] = v[i] / n1;
+          wg_sync(lo);
+          const int rest = a.power_steps - 1;
           double scale = 1.0 / f;   // the current power is scale * src
-          for (int k = 0; (a.power_steps >> k) != 0; ++k) {
-            if ((a.power_steps >> k) & 1) apply_v(src);
-            if ((a.power_steps >> (k + 1)) == 0) break;
+          for (int k = 0; (rest >> k) != 0; ++k) {
+            if ((rest >> k) & 1) apply_v(src);
+            if ((rest >> (k + 1)) == 0) break;
             // next power: (scale src)^2, tiles t = wv, wv + 4, ...
             d4 nxt[4];
             double sq = 0.0;

@@ -89,6 +89,18 @@ def test_append_hadamard_bitwise(k, q, p):
 # --------------------------------------------------------------------------
 # orth parity against the oracle
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [5, 16, 20, 33, 64, 65, 100, 128, 129, 200])
+def test_orth_first_shift_matches_oracle(n):
+    """The first shift carries ||X||_2 from the device's power iteration (by
+    squaring up to 64 columns, step by step above; X in LDS or in global
+    memory): the same estimate as the oracle's 30 steps, to rounding."""
+    A = S.test_matrix(4000, n, 1e8, seed=(60,))
+    io = O.orth(A)[2]
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0
+    assert abs(info["sigma"][0] - io["sigma"][0]) <= 1e-9 * io["sigma"][0]
+
+
 def test_orth_parity_20000x20_kappa1e6():
     A = S.test_matrix(20000, 20, 1e6, seed=(1,))
     Qo, Ro, io = O.orth(A)

@@ -155,6 +155,50 @@ def test_lambda_max_is_lower_bound_on_clustered_spectrum():
         assert 0.9 * ref <= est <= ref * (1 + 1e-13)
 
 
+def _lambda_by_squaring(X, steps=30):
+    """The device's evaluation of the same estimate: the first step X 1
+    explicitly (X 1 = 0 ends it with 0), then X^(steps-1) from powers X^(2^k)
+    (each scaled to unit Frobenius norm), then the Rayleigh quotient."""
+    v = X @ np.ones(X.shape[0])
+    n1 = np.linalg.norm(v)
+    if not (n1 > 0) or not np.isfinite(n1):
+        return 0.0 if np.isfinite(n1) else float("nan")
+    v, P, rest, k = v / n1, X / np.linalg.norm(X), steps - 1, 0
+    while rest >> k:
+        if (rest >> k) & 1:
+            v = P @ v
+        if rest >> (k + 1):
+            P = P @ P
+            P = P / np.linalg.norm(P)
+        k += 1
+    nv = np.linalg.norm(v)
+    if not (nv > 0) or not np.isfinite(nv):
+        return 0.0 if np.isfinite(nv) else float("nan")
+    v = v / nv
+    return abs(float(v @ (X @ v)))
+
+
+def test_power_iteration_by_squaring_is_the_same_estimate():
+    # The 30 normalised steps from the ones vector give X^30 1 / ||X^30 1||;
+    # forming X^30 from X^2, X^4, X^8, X^16 changes rounding only.  Also the
+    # degenerate cases: X = 0, and 1 in the null space of X (both give 0).
+    g = np.random.default_rng(17)
+    cases = []
+    for n, kappa in ((5, 1e2), (16, 1e8), (20, 1e6), (64, 1e12), (100, 1e15)):
+        A = S.test_matrix(2 * n + 50, n, kappa, seed=(8,))
+        cases.append(A.T @ A)
+    for n in (7, 33):
+        B = g.standard_normal((2 * n, n))
+        cases.append(B.T @ B * 1e6)
+    for X in cases:
+        for steps in (30, 1, 7):
+            ref = O.lambda_max(X, steps)
+            assert abs(_lambda_by_squaring(X, steps) - ref) <= 1e-12 * ref
+    assert _lambda_by_squaring(np.zeros((6, 6))) == O.lambda_max(np.zeros((6, 6))) == 0.0
+    C = np.eye(4) - np.ones((4, 4)) / 4.0        # C 1 = 0 exactly
+    assert O.lambda_max(C) == 0.0 and _lambda_by_squaring(C) == 0.0
+
+
 def test_shift_formulas_exact():
     # 11 (m n + n (n+1)) with m=1000, n=20 is 11 * 20420 = 224620; with
     # ||X|| = 1 the shift is that integer times 2^-53, exactly.
