@@ -77,16 +77,33 @@ def request_bytes(kind: str, m: int, q: int, p: int, passes: int) -> float:
     return 8.0 * m * ((q + p) + passes * (q + 2 * p))
 
 
+_V_CACHE: dict = {}
+
+
+def _rotation(k: int, device) -> torch.Tensor:
+    """V of the input recipe for width k: the Q factor of a k x k Gaussian
+    drawn from a fixed seed per k, formed once and kept (a small QR per
+    request would cap the rate at which inputs can be synthesised)."""
+    key = (k, str(device))
+    V = _V_CACHE.get(key)
+    if V is None:
+        gen = torch.Generator(device=device)
+        gen.manual_seed(7919 * 1000 + k)
+        V, _ = torch.linalg.qr(torch.randn((k, k), generator=gen, device=device, dtype=torch.float64))
+        _V_CACHE[key] = V
+    return V
+
+
 def make_input(req: Request, seed: int, device="cuda") -> torch.Tensor:
     """Seeded synthetic input of a request: G diag(s) V^T / sqrt(m) with G
-    Gaussian (m x k), V the Q factor of a Gaussian k x k matrix and s
-    log-spaced from 1 to 1/kappa, FP64, column-major (k = n or p).  G / sqrt(m)
-    has orthonormal columns up to O(sqrt(k/m)), so cond(A) is kappa to that
-    accuracy."""
+    Gaussian (m x k, from the request's seed), V the Q factor of a Gaussian
+    k x k matrix (one per width k) and s log-spaced from 1 to 1/kappa, FP64,
+    column-major (k = n or p).  G / sqrt(m) has orthonormal columns up to
+    O(sqrt(k/m)), so cond(A) is kappa to that accuracy."""
     k = req.cols
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
-    V, _ = torch.linalg.qr(torch.randn((k, k), generator=gen, device=device, dtype=torch.float64))
+    V = _rotation(k, device)
     s = torch.logspace(0.0, -math.log10(req.kappa), k, device=device, dtype=torch.float64) \
         if k > 1 else torch.ones(1, device=device, dtype=torch.float64)
     SVt = (s[:, None] * V.t()).contiguous() / math.sqrt(req.m)
