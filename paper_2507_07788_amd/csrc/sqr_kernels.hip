@@ -897,14 +897,6 @@ __device__ double block_sum(double v, double* buf, bool lds_only) {
 }
 
 
-// Broadcast lane l's double to the wave (l uniform).
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // Lane L of each row of 16 lanes to the whole row (DPP row_newbcast), in
 // vector registers.
 template <int L>
