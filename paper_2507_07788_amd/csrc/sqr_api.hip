@@ -181,10 +181,12 @@ const Variant* pick_variant(int ns) {
   return nullptr;
 }
 
-size_t block_lds_bytes() {
-  // main loop: partial T tiles + transposition tiles; the final cross-group
-  // reduction (at most 4 groups x 2 tiles, or 2 groups x 5 tiles) fits in it
-  return 8 * ((size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch);
+size_t block_lds_bytes(const Variant& v, bool apply) {
+  // main loop: partial T tiles + transposition tiles (the final cross-group
+  // reduction, at most 4 groups x 2 tiles or 2 groups x 5 tiles, fits in
+  // them); the apply adds its operands C_J (16 nt wpt rows) and D_J
+  return 8 * ((size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch +
+              (apply ? (size_t)v.nt * v.wpt * 256 + 256 : 0));
 }
 
 bool g_attr_done = false;
@@ -224,7 +226,7 @@ void set_kernel_attributes() {
     for (int ap = 0; ap < 2; ++ap) {
       int n = 1;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)(ap ? v.apply : v.gram),
-                                                        kThreads, block_lds_bytes()) != hipSuccess ||
+                                                        kThreads, block_lds_bytes(v, ap != 0)) != hipSuccess ||
           n < 1)
         n = 1;
       g_occ[ap][i] = n;
@@ -485,7 +487,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
       if (rec.e0) (void)hipEventRecord(rec.e0, s);
     }
     if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
-                        dim3(kThreads), args, block_lds_bytes(), s) != hipSuccess)
+                        dim3(kThreads), args, block_lds_bytes(*v, apply), s) != hipSuccess)
       return SQR_EHIP;
     if (g_prof_on && rec.e0 && rec.e1) {
       (void)hipEventRecord(rec.e1, s);

@@ -128,20 +128,16 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   double* tr = lds + 2 * kWaves * kTPart + wave * 16 * kYPitch;
   const int hi1 = a.n1 - 1, hi2 = a.n2 - 1;              // last column of each S segment
 
-  // A operands: -B~ rows of my k-slices (zero past the end of S) and the
-  // inverse diagonal block (k-slice r: Rinv[g+4r][x]).
-  double bn[NTW][4];
-  double rinv[4];
+  // A operands of the apply, kept in LDS (not registers, for occupancy):
+  // the rows of C_J (zero past the end of S) and the inverse diagonal block
+  // D_J; k-slice s of C_J is read as C[4s + g][x], k-slice r of D_J as
+  // D[g + 4r][x].
+  constexpr int kCop = NTW * WPT * 256;   // rows 16 NTW WPT of 16 doubles
+  double* cop = lds + 2 * kWaves * kTPart + kWaves * 16 * kYPitch;
   if (APPLY) {
-#pragma unroll
-    for (int j = 0; j < NTW; ++j)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int s = 4 * (mem + WPT * j) + jj;
-        bn[j][jj] = (s < nk) ? a.bneg[(4 * s + g) * 16 + x] : 0.0;
-      }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rinv[r] = a.rinv[(g + 4 * r) * 16 + x];
+    for (int e = threadIdx.x; e < kCop; e += kThreads) cop[e] = (e < ks * 16) ? a.bneg[e] : 0.0;
+    for (int e = threadIdx.x; e < 256; e += kThreads) cop[kCop + e] = a.rinv[e];
+    __syncthreads();
   }
 
   d4 acc[NTW];
@@ -223,18 +219,19 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
       d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
       d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
       if (mem == 0) {
-        c0 = mfma(rinv[0], w[0], c0);
-        c1 = mfma(rinv[1], w[1], c1);
-        c0 = mfma(rinv[2], w[2], c0);
-        c1 = mfma(rinv[3], w[3], c1);
+        c0 = mfma(cop[kCop + (g + 0) * 16 + x], w[0], c0);
+        c1 = mfma(cop[kCop + (g + 4) * 16 + x], w[1], c1);
+        c0 = mfma(cop[kCop + (g + 8) * 16 + x], w[2], c0);
+        c1 = mfma(cop[kCop + (g + 12) * 16 + x], w[3], c1);
       }
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
         if (mem + WPT * j < ns) {   // tile slots past the end of S hold zeros
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
-            if (jj & 1) c1 = mfma(bn[j][jj], sreg[j][jj], c1);
-            else        c0 = mfma(bn[j][jj], sreg[j][jj], c0);
+            const double bv = cop[(16 * (mem + WPT * j) + 4 * jj + g) * 16 + x];
+            if (jj & 1) c1 = mfma(bv, sreg[j][jj], c1);
+            else        c0 = mfma(bv, sreg[j][jj], c0);
           }
         }
       }
