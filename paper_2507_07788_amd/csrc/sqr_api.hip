@@ -156,6 +156,10 @@ const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
 #undef SQR_WIDE
 int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 
+// FP64 orth calls of one block (at most 16 columns): [Gram only, apply].
+const WideKernel kNarrow[2] = {narrow_pass<false>, narrow_pass<true>};
+int g_narrow_occ[2];
+
 // Orth calls of 8..16 blocks: a whole-pass apply and a Gramian kernel
 // (FP64, and FP32 for the mixed form).
 typedef void (*SplitKernel)(WidePassArgs);
@@ -263,6 +267,12 @@ void set_kernel_attributes() {
         n < 1)
       n = 1;
     g_split_occ[2][nb - kSplitMin] = n;
+  }
+  for (int ap = 0; ap < 2; ++ap) {
+    int n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kNarrow[ap], kThreads, 0) != hipSuccess || n < 1)
+      n = 1;
+    g_narrow_occ[ap] = n;
   }
   g_attr_done = true;
 }
@@ -401,6 +411,37 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
                  launch((const void*)kSplit[idx].gram, nwg, kGramThreads, split_lds_bytes((int)P, false));
         }))
       return SQR_EHIP;
+  } else if (c.mode == 0 && P == 1 && !mixed) {
+    // one block: the whole pass in one launch, every wave on its own tiles
+    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_narrow_occ[apply ? 1 : 0]);
+    nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, (tiles + kWaves - 1) / kWaves));
+    WidePassArgs w;
+    memset(&w, 0, sizeof(w));
+    w.win = (apply && phase > 1) ? c.y : c.win;
+    w.ldw = (apply && phase > 1) ? c.ldy : c.ldw;
+    w.yout = c.y; w.ldy = c.ldy;
+    w.n = (int)c.p; w.m = b->m;
+    w.rinv = b->rinv;
+    w.part = b->part; w.part_stride = tl;
+    w.done = phase > 0 ? &b->ctrl->done : nullptr;
+    w.passes = &b->ctrl->passes;
+    w.copy_if_done = (phase == 1);
+    void* args[] = {&w};
+    ProfRec rec{};
+    if (g_prof_on) {
+      rec.e0 = take_event(); rec.e1 = take_event();
+      rec.kind = apply ? 1 : 0;
+      rec.bytes = 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0);
+      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
+      if (rec.e0) (void)hipEventRecord(rec.e0, s);
+    }
+    if (hipLaunchKernel((const void*)kNarrow[apply ? 1 : 0], dim3((unsigned)nwg), dim3(kThreads), args, 0, s) !=
+        hipSuccess)
+      return SQR_EHIP;
+    if (g_prof_on && rec.e0 && rec.e1) {
+      (void)hipEventRecord(rec.e1, s);
+      g_prof.push_back(rec);
+    }
   } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
     // precision from pass 1 on; the one that does not match the device's

@@ -374,6 +374,127 @@ __device__ __forceinline__ int64_t e_off(int q4, int J) {
 }
 
 // ---------------------------------------------------------------------------
+// narrow_pass: one launch per pass of an FP64 orth call of at most 16
+// columns.  With one block the apply is Y = W D (D the inverse of R~, the
+// identity for the Gram-only pass) and the Gramian is Y^T Y.  The same
+// registers give both layouts without transposes: with lane (x, g), reg s
+// holding W[row x][col 4s + g] and D[4s + g][x],
+//   sum_s mfma(w_s, d_s) = W D,     reg r = Y[row g + 4r][col x]
+//                                   (the A and B operand layout of Y^T Y),
+//   sum_s mfma(d_s, w_s) = D^T W^T, reg r = Y[row x][col g + 4r]
+//                                   (rows across lanes: coalesced stores).
+// Every wave works on its own row tiles (tile t0 + wave + 4k of the
+// workgroup's range) with kNarrowPF tiles in flight, and no barrier until
+// the four wave Gramians are summed in wave order into the workgroup's slot.
+// ---------------------------------------------------------------------------
+constexpr int kNarrowPF = 4;
+
+template <bool APPLY>
+__global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
+  __shared__ double red[kWaves * 256];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t t1 = min(tiles, t0 + per);
+
+  if (a.done && *a.done) {
+    if (APPLY && a.copy_if_done && *a.passes == 0) {
+      for (int64_t t = t0 + wave; t < t1; t += kWaves) {
+        const int64_t row = t * 16 + x;
+        if (row >= a.m) continue;
+        for (int c = g; c < a.n; c += 4)
+          a.yout[(int64_t)c * a.ldy + row] = a.win[(int64_t)c * a.ldw + row];
+      }
+    }
+    return;
+  }
+
+  double dv[4];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4)
+    dv[s4] = APPLY ? a.rinv[(4 * s4 + g) * 16 + x] : ((4 * s4 + g == x) ? 1.0 : 0.0);
+
+  // W tile: reg r = W[row x][col g + 4r] as loaded; columns past n read
+  // zero (buffer range).  Rows past m and tiles past the range (t1) are
+  // cleared by the mask `keep` when the tile is used, not at the load, so the
+  // loads stay in flight until then.
+  auto load = [&](int64_t tile, d4& w, uint64_t& keep) {
+    const int64_t row = min(tile, t1 - 1) * 16 + x;
+    keep = (row < a.m && tile < t1) ? ~0ull : 0ull;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
+    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t nrec = (a.n - 1 >= 4 * r) ? (((int64_t)(a.n - 1 - 4 * r) * a.ldw + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(4 * r) * a.ldw, nrec);
+      w[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
+    }
+  };
+  auto masked = [](double v, uint64_t keep) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep);
+  };
+
+  d4 accg = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t first = t0 + wave;
+  if (first < t1) {
+    d4 wb[kNarrowPF];
+    uint64_t kb[kNarrowPF];
+#pragma unroll
+    for (int q = 0; q < kNarrowPF; ++q) load(first + kWaves * q, wb[q], kb[q]);
+    for (int64_t k0 = 0; first + kWaves * k0 < t1; k0 += kNarrowPF) {
+#pragma unroll
+      for (int q = 0; q < kNarrowPF; ++q) {
+        // wb[q] is used first and then refilled with the tile kNarrowPF
+        // steps ahead: the load lands in the same registers, so no copy (and
+        // no wait for the loads in flight) is needed at the loop's end.  A
+        // tile past the range holds zeros: no branch around the arithmetic.
+        const int64_t tile = first + kWaves * (k0 + q);
+        __builtin_amdgcn_sched_barrier(0);   // keep this slot's wait here, not hoisted
+        d4 w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = masked(wb[q][r], kb[q]);
+        {
+          d4 ya = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) ya = mfma(w[s4], dv[s4], ya);
+          if (APPLY) {
+            d4 yb = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) yb = mfma(dv[s4], w[s4], yb);
+            const int64_t row = tile * 16 + x;
+            if (tile < t1 && row < a.m) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int col = g + 4 * r;
+                if (col < a.n) a.yout[(int64_t)col * a.ldy + row] = yb[r];
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) accg = mfma(ya[u], ya[u], accg);
+        }
+        load(tile + kWaves * kNarrowPF, wb[q], kb[q]);
+      }
+    }
+  }
+  // Gramian slot of the workgroup: element (i, j) at i * 16 + j, the wave
+  // partials added in wave order.
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + (g + 4 * r) * 16 + x] = accg[r];
+  __syncthreads();
+  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+  for (int e = threadIdx.x; e < 256; e += kThreads) {
+    double t = 0.0;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) t += red[v * 256 + e];
+    out[e] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // wide_pass: one launch per pass of an orth call whose n columns form NB
 // blocks (2 <= NB <= 8).  Same arithmetic as the per-block launches
 // (Y_J = W_J D_J + sum_{I<J} Y_I C_IJ, then the Gramian of Y), but a wave
