@@ -325,6 +325,36 @@ def test_orth_mixed_parity(m, n, kappa):
     _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
 
 
+@pytest.mark.slow
+def test_mixed_error_against_fp64_oracle_table():
+    """Mixed and FP64 forms against the FP64 oracle over the C3 grid
+    (n in {16, 64, 128}, kappa in {1e4, 1e8, 1e12, 1e15}) at m = 1e5: the
+    relative error of R (graded where R is unique, kappa < 1e12), LOO and RRR
+    of each result; the table is printed (pytest -s)."""
+    m = 100_000
+    rows = []
+    for n in (16, 64, 128):
+        for kappa in (1e4, 1e8, 1e12, 1e15):
+            A = S.test_matrix(m, n, kappa, seed=(70, n))
+            Qo, Ro, io = O.orth(A)
+            line = [n, kappa, io["passes"]]
+            for precision in (0, 1):
+                b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(precision=precision))
+                assert info["status"] == 0
+                Qg, Rg = host(b.q()), host(b.r())
+                err = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+                loo, rrr = O.loo(Qg), O.rrr(A, Qg, Rg)
+                assert loo <= 1e-12 and rrr <= 1e-13
+                if kappa < 1e12:
+                    assert err <= 1e-10 * kappa
+                line += [info["passes"], err, loo, rrr]
+                sq.sqr_free(b)
+            rows.append(line)
+    print("\n   n   kappa  oracle | FP64: passes  R err    LOO      RRR   | mixed: passes  R err    LOO      RRR")
+    for r in rows:
+        print("%4d %7.0e %5d   | %6d  %8.1e %8.1e %8.1e | %6d  %8.1e %8.1e %8.1e" % tuple(r))
+
+
 def test_orth_mixed_limits():
     A = dev(S.test_matrix(1000, 257, 10.0, seed=(14,)))
     with pytest.raises(RuntimeError):
