@@ -442,8 +442,13 @@ __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
   if (first < t1) {
     d4 wb[kNarrowPF];
     uint64_t kb[kNarrowPF];
+    // loads issued slot after slot (as in the loop), so that the waits at
+    // the loop head are counted per slot
 #pragma unroll
-    for (int q = 0; q < kNarrowPF; ++q) load(first + kWaves * q, wb[q], kb[q]);
+    for (int q = 0; q < kNarrowPF; ++q) {
+      load(first + kWaves * q, wb[q], kb[q]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     for (int64_t k0 = 0; first + kWaves * k0 < t1; k0 += kNarrowPF) {
 #pragma unroll
       for (int q = 0; q < kNarrowPF; ++q) {
