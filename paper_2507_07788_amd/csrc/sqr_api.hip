@@ -537,7 +537,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   }
   }
   // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
-  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + 63) / 64)), dim3(64 * kRedWaves), 0, s,
+  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + kRedElems - 1) / kRedElems)), dim3(64 * kRedWaves), 0, s,
                      (const double*)b->part, (int)nwg, tl, tl, b->stage,
                      phase > 0 ? (const int*)&b->ctrl->done : (const int*)nullptr);
   SmallArgs k;

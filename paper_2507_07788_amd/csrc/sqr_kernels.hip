@@ -337,32 +337,38 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   }
 }
 
-// Sum the nslots partial slots element-wise: a workgroup covers 64 elements
-// (one per lane, coalesced); its 16 waves take interleaved slots, each in
-// slot order, and the 16 wave sums are added in wave order.  The order of
-// every addition is fixed by nslots alone.
+// Sum the nslots partial slots element-wise.  A workgroup covers kRedElems
+// elements; lane (sub, e) of wave w reads element e of slots
+// 4w + sub + 64k, k = 0, 1, ... (each load instruction takes 128 contiguous
+// bytes from four slots), summing them in k order; the four sub-sums of a
+// wave are added by a fixed butterfly, and the 16 wave sums in wave order.
+// The order of every addition is fixed by nslots alone.
 constexpr int kRedWaves = 16;
+constexpr int kRedElems = 16;
 __global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __restrict__ in,
                                                              int nslots, int64_t stride,
                                                              int64_t len,
                                                              double* __restrict__ out,
                                                              const int* done) {
-  __shared__ double part[kRedWaves][64];
+  __shared__ double part[kRedWaves][kRedElems];
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int e = lane & (kRedElems - 1), sub = lane >> 4;
+  const int64_t el = (int64_t)blockIdx.x * kRedElems + e;
   double s = 0.0;
-  if (e < len) {
-#pragma unroll 8
-    for (int i = wv; i < nslots; i += kRedWaves) s += in[(int64_t)i * stride + e];
+  if (el < len) {
+#pragma unroll 4
+    for (int i = 4 * wv + sub; i < nslots; i += 4 * kRedWaves) s += in[(int64_t)i * stride + el];
   }
-  part[wv][lane] = s;
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  if (sub == 0) part[wv][e] = s;
   __syncthreads();
-  if (wv == 0 && e < len) {
+  if (wv == 0 && sub == 0 && el < len) {
     double t = 0.0;
 #pragma unroll
-    for (int v = 0; v < kRedWaves; ++v) t += part[v][lane];
-    out[e] = t;
+    for (int v = 0; v < kRedWaves; ++v) t += part[v][e];
+    out[el] = t;
   }
 }
 

@@ -264,8 +264,11 @@ def test_append_nearly_dependent_shifts(q, p, eps):
     info = sq.sqr_append(b, dev(W))
     assert info["status"] == 0 and b.n == q + p
     assert abs(info["passes"] - io["passes"]) <= 1
+    # X is at the rounding level here, so where the x10 escalation first
+    # factorises depends on rounding: one attempt, one factor of 10 in sigma
     assert abs(info["chol_attempts"] - io["chol_attempts"]) <= 1
-    assert abs(info["sigma"][0] - io["sigma"][0]) <= 1e-2 * io["sigma"][0]
+    ratio = info["sigma"][0] / io["sigma"][0]
+    assert min(abs(ratio - 1.0), abs(ratio - 10.0), abs(ratio - 0.1)) <= 1e-2 * max(ratio, 1.0)
     A = np.concatenate([A1, W], axis=1)
     Qg, Rg = host(b.q()), host(b.r())
     assert O.loo(Qg) <= 1e-12 and O.rrr(A, Qg, Rg) <= 1e-13
