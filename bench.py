@@ -167,7 +167,8 @@ def main():
     traffic = measured_traffic(by / max(nl, 1))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "block_pass (apply)", "launches": nl,
+                "kernel": "apply launches: block_pass (narrow_pass for the 10-column start)",
+                "launches": nl,
                 "avg_launch_us": round(ms * 1e3 / max(nl, 1), 2),
                 "algorithmic_bytes_per_launch": round(by / max(nl, 1))}
 
