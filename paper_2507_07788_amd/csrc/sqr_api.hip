@@ -1,12 +1,19 @@
 // sqr_api.hip -- host driver of libsqr: the C ABI declared in include/sqr.h.
 //
 // A call enqueues, on the caller's stream, an initial Gram pass and then
-// Cholesky QR passes (block_pass launches per 16-column block, a fixed-order
-// reduction of the per-workgroup partial Gramians, one small_step).  The
-// convergence decision is taken on the device; kernels of later passes exit
-// at once after it.  With a host `info` the driver enqueues the passes the
-// method normally needs, reads the device state once, and adds passes only
-// when the device asks for them.
+// Cholesky QR passes: the streaming kernels of the pass, a fixed-order
+// reduction of the per-workgroup partial Gramians (reduce_slots) and one
+// small_step.  The streaming kernels of a pass, by call and width (16-column
+// blocks P):
+//   orth, FP64, P = 1        narrow_pass (apply and Gramian in one launch)
+//   orth, P = 2..7 (mixed 1..8)  wide_pass (one launch per pass)
+//   orth, P = 8..16 (mixed 9..16)  wide_apply, then gram_pass (FP32 variant
+//                            for the mixed form's early passes)
+//   appends; orth, P > 16    block_pass, one launch per block
+// The convergence decision is taken on the device; kernels of later passes
+// exit at once after it.  With a host `info` the driver enqueues the passes
+// the method normally needs, reads the device state once, and adds passes
+// only when the device asks for them.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -2,7 +2,8 @@
 // Cholesky QR block append (arXiv 2507.07788, Algorithms 1 and 2).
 //
 // The tall operands stay in HBM, column-major.  A pass over them is split
-// into 16-column blocks.  For block J one launch of `block_pass` streams
+// into 16-column blocks.  In the general form (appends, and orthogonalisations
+// wider than 256 columns) one launch of `block_pass` per block J streams
 // 16-row tiles and, per tile,
 //   (1) forms Y_J = W_J D_J + S C_J, where D_J is the inverse of the 16x16
 //       diagonal block of R~ and C_J = -[B~_J; R~_<J,J] D_J: the
@@ -14,11 +15,14 @@
 //       Q^T Q), so every pass reads the tall data once.
 // S is the concatenation of the existing basis Q_in and the blocks < J of the
 // same pass.  All contractions run on v_mfma_f64_16x16x4f64.  Every workgroup
-// writes its partial Gramian to its own slot; slots are summed in a fixed
-// tree order (no atomics), so results do not depend on scheduling.
+// writes its partial Gramian to its own slot; `reduce_slots` sums the slots
+// in a fixed order (no atomics), so results do not depend on scheduling.
+// Orthogonalisations of up to 256 columns have whole-pass kernels with the
+// same arithmetic: `narrow_pass` (one block), `wide_pass` (up to 8 blocks),
+// `wide_apply` + `gram_pass` (8 to 16 blocks).
 //
-// `small_step` is a one-workgroup kernel that finishes a pass: it reduces the
-// Gramian, forms the Schur complement X = G - B~^T B~ (Prop. 2.1), tests
+// `small_step` is a one-workgroup kernel that finishes a pass: from the
+// reduced Gramian it forms the Schur complement X = G - B~^T B~ (Prop. 2.1), tests
 // ||X - I||_F, picks the shift (Algorithm 1: recomputed from ||X||_2;
 // Algorithm 2: x10 escalation), factors X + sigma I, updates R and B, and
 // prepares the operands of the next pass.  Control decisions stay on the
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
 
 // ---------------------------------------------------------------------------
 // wide_pass: one launch per pass of an orth call whose n columns form NB
-// blocks (2 <= NB <= 8).  Same arithmetic as the per-block launches
+// blocks (2 <= NB <= 7 in FP64; 1 <= NB <= 8 in the mixed form).  Same arithmetic as the per-block launches
 // (Y_J = W_J D_J + sum_{I<J} Y_I C_IJ, then the Gramian of Y), but a wave
 // keeps the Y blocks of its 16-row tile in registers, so the prefix Y_<J is
 // never re-read from HBM: the pass reads W once and writes Y once.
