@@ -55,7 +55,10 @@ typedef struct sqr_opts {
   double  tol;              /* stop when ||X - I||_F < tol, default 1e-13       */
   double  unit_roundoff;    /* u in the shift formulas, default 2^-53           */
   int32_t max_escalations;  /* cap on the x10 shift escalations, default 32     */
-  int32_t power_steps;      /* power-iteration steps for ||X||_2, default 30    */
+  int32_t power_steps;      /* power-iteration steps for ||X||_2 from the
+                               all-ones vector, 1..1000, default 30 (for
+                               p <= 64 the same iterate X^s 1 is formed from
+                               powers of X by repeated squaring)              */
 } sqr_opts;
 
 /* Outcome of one call (host struct). */
