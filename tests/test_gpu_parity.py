@@ -358,6 +358,45 @@ def test_mixed_error_against_fp64_oracle_table():
         print("%4d %7.0e %5d   | %6d  %8.1e %8.1e %8.1e | %6d  %8.1e %8.1e %8.1e" % tuple(r))
 
 
+def test_park_returns_workspace_and_results_are_unchanged():
+    """sqr_park hands an idle handle's scratch back to the pool; the next call
+    on the handle takes a workspace again.  Same kernels, same order: the
+    parked run equals the unparked one bit for bit."""
+    A = S.test_matrix(5000, 24, 1e5, seed=(80,))
+    W = S.test_matrix(5000, 8, 1e3, seed=(81,))
+    out = []
+    for park in (False, True):
+        b, info = sq.sqr_orth(dev(A), cap=32)
+        assert info["status"] == 0
+        if park:
+            sq.sqr_park(b)
+            sq.sqr_park(b)          # parking a parked handle does nothing
+        info = sq.sqr_append(b, dev(W))
+        assert info["status"] == 0 and b.n == 32
+        out.append((host(b.q()), host(b.r())))
+        sq.sqr_free(b)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_prof_hooks_count_launches():
+    """sqr_prof_enable / sqr_prof_read: HIP events around each streaming
+    launch, folded into Gram-only and apply launches with their bytes."""
+    m, n = 200_000, 48
+    A = dev(S.test_matrix(m, n, 1e4, seed=(82,)))
+    sq.sqr_prof_read()                      # drop earlier records
+    sq.sqr_prof_enable(True)
+    b, info = sq.sqr_orth(A)
+    prof = sq.sqr_prof_read()
+    sq.sqr_prof_enable(False)
+    sq.sqr_free(b)
+    ng, msg, bg = prof["gram"]
+    na, msa, ba = prof["apply"]
+    x = info["passes"]
+    assert ng == 1 and na == x                     # one Gram-only pass, x applies
+    assert bg == 8.0 * m * n and ba == x * 16.0 * m * n
+    assert msg > 0 and msa > 0
+
+
 def test_orth_mixed_limits():
     A = dev(S.test_matrix(1000, 257, 10.0, seed=(14,)))
     with pytest.raises(RuntimeError):
