@@ -358,6 +358,24 @@ def test_mixed_error_against_fp64_oracle_table():
         print("%4d %7.0e %5d   | %6d  %8.1e %8.1e %8.1e | %6d  %8.1e %8.1e %8.1e" % tuple(r))
 
 
+@pytest.mark.parametrize("start", ["alg1", "cholqr3"])
+def test_fig1_pattern_on_the_device(start):
+    """Fig. 1's robustness pattern through the library: 300 x 10 inputs with
+    kappa from 1 to 1e20 reach the stopping tolerance (LOO <= 1e-13, the
+    Sec. 3.1 criterion), with Algorithm 1 as printed and with the CholQR3
+    start, in as many passes as the oracle (+-1)."""
+    kw = dict(first_pass_shift=0, min_passes=0) if start == "alg1" else {}
+    for e in range(0, 21, 2):
+        A = S.test_matrix(300, 10, 10.0 ** e, seed=(6,))
+        _, _, io = O.orth(A, **kw)
+        b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+        assert info["status"] == 0 and info["passes"] <= 10, e
+        assert abs(info["passes"] - io["passes"]) <= 1, e
+        Qg, Rg = host(b.q()), host(b.r())
+        assert O.loo(Qg) <= 1e-13 and O.rrr(A, Qg, Rg) <= 1e-13, e
+        sq.sqr_free(b)
+
+
 def test_park_returns_workspace_and_results_are_unchanged():
     """sqr_park hands an idle handle's scratch back to the pool; the next call
     on the handle takes a workspace again.  Same kernels, same order: the
