@@ -114,7 +114,8 @@ def shift_orth(m: int, n: int, xnorm: float, u: float = U64) -> float:
 def shift_append_first(m: int, q: int, xnorm: float, u: float = U64) -> float:
     """First shift of Algorithm 2: 11 (m q + q (q+1)) u ||X||, floored at 2u.
 
-    Algorithm 2 uses q, the width of the existing basis, in this formula.
+    Algorithm 2 uses q, the width of the existing basis, in this formula (the
+    append driver's option append_shift_dim substitutes p or q + p).
     """
     return max(11.0 * float(m * q + q * (q + 1)) * u * xnorm, 2.0 * u)
 
@@ -151,15 +152,20 @@ def apply_inverse(T: np.ndarray, Rt: np.ndarray) -> np.ndarray:
 
 
 def _chol_with_escalation(X: np.ndarray, sigma0: float, u: float,
-                          max_escalations: int):
-    """chol(X + sigma I), sigma <- 10 sigma (floored at 2u) until it succeeds.
+                          max_escalations: int, tries: list | None = None):
+    """chol(X + sigma I) from sigma = max(sigma0, 2u); after each breakdown
+    sigma <- max(10 sigma, 2u) (Algorithm 2, inner loop), at most
+    max_escalations times.
 
-    Returns (R~, sigma, attempts, ok)."""
+    Returns (R~, sigma, attempts, ok); every shift tried is appended to
+    `tries` when given."""
     n = X.shape[0]
     sigma = max(sigma0, 2.0 * u)
     attempts = 0
     while True:
         attempts += 1
+        if tries is not None:
+            tries.append(sigma)
         Rt, ok = cholesky_upper(X + sigma * np.eye(n))
         if ok:
             return Rt, sigma, attempts, True
@@ -171,13 +177,37 @@ def _chol_with_escalation(X: np.ndarray, sigma0: float, u: float,
 # --------------------------------------------------------------------------
 # drivers
 # --------------------------------------------------------------------------
+#: shift policies of the orth driver (option ``shift_policy``)
+RECOMPUTE = 0   # Algorithm 1 (rsCholQR): recompute sigma from the current X
+NO_SHIFT = 1    # CholQR / CholQR2 (and shiftedCholeskyQR3 after its first pass)
+FIXED = 2       # isCholQR: sigma from the input Gramian, reapplied
+
+
 def default_opts(**kw) -> dict:
     """Options of the drivers; defaults give CholQR3 (a shifted first pass,
     then CholeskyQR2, then Algorithm 1's continuation)."""
     opts = dict(first_pass_shift=1, min_passes=3, max_iter=10, tol=1e-13,
-                unit_roundoff=U64, max_escalations=32, power_steps=30, precision=0)
+                unit_roundoff=U64, max_escalations=32, power_steps=30, precision=0,
+                shift_policy=RECOMPUTE, append_shift_dim=0)
     opts.update(kw)
     return opts
+
+
+#: option sets of the Cholesky QR variants compared in Sec. 3.2 (Fig. 1)
+VARIANTS = {
+    # one pass, no shift: a breakdown ends the call
+    "CholQR": dict(first_pass_shift=0, min_passes=1, max_iter=1, shift_policy=NO_SHIFT),
+    # two plain passes
+    "CholQR2": dict(first_pass_shift=0, min_passes=2, max_iter=2, shift_policy=NO_SHIFT),
+    # a shifted pass followed by two plain ones, nothing more
+    "sCholQR3": dict(first_pass_shift=1, min_passes=3, max_iter=3, shift_policy=NO_SHIFT),
+    # plain passes until the test holds, the shift from ||A||^2 on a breakdown
+    "isCholQR": dict(first_pass_shift=0, min_passes=0, max_iter=10, shift_policy=FIXED),
+    # Algorithm 1 as printed
+    "rsCholQR": dict(first_pass_shift=0, min_passes=0, max_iter=10, shift_policy=RECOMPUTE),
+    # the shifted pass, CholeskyQR2, then Algorithm 1's test and continuation
+    "CholQR3": dict(first_pass_shift=1, min_passes=3, max_iter=10, shift_policy=RECOMPUTE),
+}
 
 
 def orth(A: np.ndarray, **kw):
@@ -189,11 +219,23 @@ def orth(A: np.ndarray, **kw):
     plain Cholesky factorisation of the current Gramian breaks down, with the
     shift recomputed from the current Gramian (Algorithm 1, shift step).
 
+    ``shift_policy`` selects the other variants of Sec. 3.1 (see VARIANTS):
+    NO_SHIFT ends the call on a breakdown (and a shifted first pass does not
+    escalate); FIXED computes sigma = max{11 (mn + n(n+1)) u ||X_0||, 2u} once
+    from the input Gramian X_0 = A^T A (||X_0|| = ||A||^2) and factors
+    X + sigma I with it whenever the plain factorisation breaks down, ending
+    the call if that fails too.
+
     Returns (Q, R, info) with info = dict(status, passes, sigma, chol_attempts,
     orth_fro).  ``first_pass_shift=0, min_passes=0`` is Algorithm 1 as printed.
     """
     o = default_opts(**kw)
     u = o["unit_roundoff"]
+    policy = int(o["shift_policy"])
+    if policy not in (RECOMPUTE, NO_SHIFT, FIXED):
+        raise ValueError("shift_policy")
+    if policy != RECOMPUTE and int(o["precision"]) != 0:
+        raise ValueError("the variants of shift_policy run in FP64 only")
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     Q = A.copy()
@@ -201,7 +243,10 @@ def orth(A: np.ndarray, **kw):
     g32 = int(o["precision"]) == 1      # the Gramian at hand is an FP32 one
     X = gram_fp32(Q) if g32 else gram(Q)
     info = dict(status=OK, passes=0, sigma=[], chol_attempts=0, orth_fro=None,
-                fp32_grams=int(g32))
+                fp32_grams=int(g32), shift_tries=[])
+    sigma_fixed = None
+    if policy == FIXED:
+        sigma_fixed = shift_orth(m, n, lambda_max(X, o["power_steps"]), u)
     passes = 0
     while True:
         err = fro_dist_identity(X)
@@ -217,22 +262,29 @@ def orth(A: np.ndarray, **kw):
         passes += 1
         shifted = passes == 1 and bool(o["first_pass_shift"])
         sigma = 0.0
+        ok = True
         if not shifted:
             info["chol_attempts"] += 1
             Rt, ok = cholesky_upper(X)
-            shifted = not ok
-        if shifted:
+            shifted = not ok and policy != NO_SHIFT
+        if shifted and policy == FIXED:
+            sigma = sigma_fixed
+            info["shift_tries"].append(sigma)
+            info["chol_attempts"] += 1
+            Rt, ok = cholesky_upper(X + sigma * np.eye(n))
+        elif shifted:
             lam = lambda_max(X, o["power_steps"])
+            esc = o["max_escalations"] if policy == RECOMPUTE else 0
             if g32:
-                Rt, sigma, att, ok = _chol_with_escalation(X, shift_fp32(n, lam), U32,
-                                                           o["max_escalations"])
+                Rt, sigma, att, ok = _chol_with_escalation(X, shift_fp32(n, lam), U32, esc,
+                                                           info["shift_tries"])
             else:
-                Rt, sigma, att, ok = _chol_with_escalation(X, shift_orth(m, n, lam, u), u,
-                                                           o["max_escalations"])
+                Rt, sigma, att, ok = _chol_with_escalation(X, shift_orth(m, n, lam, u), u, esc,
+                                                           info["shift_tries"])
             info["chol_attempts"] += att
-            if not ok:
-                info["status"] = BREAKDOWN
-                break
+        if not ok:
+            info["status"] = BREAKDOWN
+            break
         info["sigma"].append(sigma)
         Q = apply_inverse(Q, Rt)
         R = Rt @ R
@@ -248,6 +300,13 @@ def append(Q_in: np.ndarray, R_in: np.ndarray, A_in: np.ndarray, **kw):
 
     Returns (Q_out, R_out, info); Q_out = [Q_in, Q], R_out = [[R_in, B],[0, R]]
     (Prop. 2.1).  The loop tests only the Schur complement X of the new block.
+
+    Reading: the stopping test is consulted only after the first pass.  Prop.
+    2.1 forms the new columns by the projection (A_in - Q_in Q_in^T A_in) R^-1;
+    the initial X can equal I while Q_in^T A_in is not zero (A_in = Q_in C + H
+    with H orthonormal and orthogonal to Q_in gives X = I exactly), and the
+    loop as printed would then return Q = A_in, which is not orthogonal to
+    Q_in.  One pass always applies the projection.
     """
     o = default_opts(**kw)
     u = o["unit_roundoff"]
@@ -260,7 +319,8 @@ def append(Q_in: np.ndarray, R_in: np.ndarray, A_in: np.ndarray, **kw):
     R = np.eye(p)
     Bt, G = gram_append(Q_in, Q)
     X = schur(G, Bt)
-    info = dict(status=OK, passes=0, sigma=[], chol_attempts=0, orth_fro=None)
+    info = dict(status=OK, passes=0, sigma=[], chol_attempts=0, orth_fro=None,
+                shift_tries=[])
     passes = 0
     while True:
         err = fro_dist_identity(X)
@@ -268,7 +328,7 @@ def append(Q_in: np.ndarray, R_in: np.ndarray, A_in: np.ndarray, **kw):
         if not math.isfinite(err):
             info["status"] = ENONFINITE
             break
-        if err < o["tol"]:
+        if passes >= 1 and err < o["tol"]:
             break
         if passes >= o["max_iter"]:
             info["status"] = NOT_CONVERGED
@@ -279,9 +339,11 @@ def append(Q_in: np.ndarray, R_in: np.ndarray, A_in: np.ndarray, **kw):
         Rt, ok = cholesky_upper(X)
         if not ok:
             lam = lambda_max(X, o["power_steps"])
-            sigma0 = shift_append_first(m, q, lam, u)
+            d = (q, p, q + p)[int(o["append_shift_dim"])]
+            sigma0 = shift_append_first(m, d, lam, u)
             Rt, sigma, att, ok = _chol_with_escalation(X, sigma0, u,
-                                                       o["max_escalations"])
+                                                       o["max_escalations"],
+                                                       info["shift_tries"])
             info["chol_attempts"] += att
             if not ok:
                 info["status"] = BREAKDOWN

@@ -425,6 +425,228 @@ def test_growth_run_small():
 
 
 # --------------------------------------------------------------------------
+# shift escalation, its floor and cap (Algorithm 2, inner loop; read into
+# Algorithm 1 for a shifted factorisation that still breaks down)
+# --------------------------------------------------------------------------
+def test_escalation_sequence_exact():
+    """X = diag(1, -delta): chol(X + sigma I) succeeds exactly when
+    sigma > delta, so the shifts tried are sigma0 f^k (f the paper's factor)
+    up to the first one above delta."""
+    f = GOLDEN["escalation_factor"]["value"]
+    X = np.diag([1.0, -999.5])
+    tries = []
+    _, sig, att, ok = O._chol_with_escalation(X, 1.0, U, 32, tries)
+    assert ok and att == 4 and sig == f ** 3
+    assert tries == [1.0, f, f * f, f ** 3]
+    tries = []
+    _, sig, att, ok = O._chol_with_escalation(X, 0.3, U, 32, tries)
+    want = [0.3]
+    while want[-1] <= 999.5:
+        want.append(want[-1] * f)
+    assert ok and tries == want and att == 5 and sig == want[-1]
+
+
+def test_escalation_cap():
+    """max_escalations bounds the x10 steps: the call fails after 1 + cap
+    attempts, and a cap of zero allows the first shifted attempt only."""
+    X = np.diag([1.0, -999.5])
+    tries = []
+    _, _, att, ok = O._chol_with_escalation(X, 1.0, U, 2, tries)
+    assert not ok and att == 3 and tries == [1.0, 10.0, 100.0]
+    _, _, att, ok = O._chol_with_escalation(X, 1.0, U, 0)
+    assert not ok and att == 1
+    _, _, att, ok = O._chol_with_escalation(X, 1.0, U, 3)
+    assert ok and att == 4
+
+
+def test_escalation_floor():
+    """The shift never starts below 2u (Algorithm 2, the max with 2u): a zero
+    or tiny first estimate starts at 2u.  With X = diag(1, -5u) the tries are
+    2u, 20u.  (The same max after a x10 step can never bind: every shift is
+    already at least 2u, so ten times it is at least 20u.)"""
+    X = np.diag([1.0, -5.0 * U])
+    for s0 in (0.0, 1e-300, U):
+        tries = []
+        _, sig, att, ok = O._chol_with_escalation(X, s0, U, 32, tries)
+        assert ok and att == 2 and tries == [2 * U, 20 * U] and sig == 20 * U
+
+
+def _dup_hadamard(k=4):
+    """[h1, h1, h2, h3] of a Sylvester Hadamard matrix of order 4^k: an exact
+    integer Gramian with the zero pivot 256 - 16 * 16 = 0 in column 2."""
+    H = S.hadamard(4 ** k)
+    return np.stack([H[:, 1], H[:, 1], H[:, 2], H[:, 3]], axis=1)
+
+
+def test_orth_breakdown_at_the_escalation_cap():
+    """Algorithm 1 as printed on exactly dependent columns with u = 2^-80: the
+    shifts sigma0 10^k stay below half an ulp of the Gramian's entries for
+    k <= 3, so X + sigma I rounds to X and every factorisation meets the same
+    exact zero pivot.  With a cap of c escalations the call ends with
+    SQR_BREAKDOWN after 1 + (1 + c) factorisations; the shifts tried are
+    sigma0, 10 sigma0, ... with sigma0 the Algorithm 1 shift of ||X||_2 = 512."""
+    A = _dup_hadamard()
+    m, n = A.shape
+    u = 2.0 ** -80
+    X = O.gram(A)
+    assert X[0, 0] == X[0, 1] == X[1, 1] == 256.0
+    sig0 = 11.0 * (m * n + n * (n + 1)) * u * 512.0
+    for cap in (0, 1, 3):
+        _, _, info = O.orth(A, first_pass_shift=0, min_passes=0, unit_roundoff=u,
+                            max_escalations=cap)
+        assert info["status"] == O.BREAKDOWN and info["passes"] == 1
+        assert info["chol_attempts"] == 2 + cap
+        assert len(info["shift_tries"]) == 1 + cap
+        for k, s in enumerate(info["shift_tries"]):
+            assert abs(s - sig0 * 10.0 ** k) <= 1e-12 * s
+        # the shifted matrices really are X (sigma below half an ulp of 256)
+        assert 256.0 + info["shift_tries"][-1] == 256.0
+    # with the default cap the shift grows past the rounding level and the
+    # factorisation succeeds
+    _, _, info = O.orth(A, first_pass_shift=0, min_passes=0, unit_roundoff=u)
+    assert info["status"] != O.BREAKDOWN
+
+
+def test_append_breakdown_keeps_basis():
+    """Two identical new columns orthogonal to Q_in: X = [[1, 1], [1, 1]]
+    exactly, whose factorisation meets a zero pivot; with u = 2^-80 the shift
+    stays below half an ulp of 1, so a cap of zero ends the call with
+    SQR_BREAKDOWN after two factorisations, and Q_out/R_out are the input."""
+    k, q = 4, 6
+    H = S.hadamard(4 ** k)
+    Qin = H[:, :q] / 2.0 ** k
+    h = H[:, q] / 2.0 ** k
+    W = np.stack([h, h], axis=1)
+    for cap in (0, 2):
+        Qo, Ro, info = O.append(Qin, np.eye(q), W, unit_roundoff=2.0 ** -80,
+                                max_escalations=cap)
+        assert info["status"] == O.BREAKDOWN and info["passes"] == 1
+        assert info["chol_attempts"] == 2 + cap
+        assert np.array_equal(Qo[:, :q], Qin)
+
+
+def test_append_first_shift_dimension():
+    """Algorithm 2's first shift 11 (m d + d (d+1)) u ||X|| with d = q as
+    printed, or p, or q + p (option append_shift_dim).  The duplicated column
+    pair above has ||X||_2 = 2, so each first shift is an integer times
+    2^-52 (to the rounding of the power iteration's Rayleigh quotient)."""
+    k, q = 4, 6
+    m = 4 ** k
+    H = S.hadamard(m)
+    Qin = H[:, :q] / 2.0 ** k
+    h = H[:, q] / 2.0 ** k
+    W = np.stack([h, h], axis=1)
+    for dim, d in ((0, q), (1, 2), (2, q + 2)):
+        _, _, info = O.append(Qin, np.eye(q), W, append_shift_dim=dim)
+        want = math.ldexp(11 * (m * d + d * (d + 1)), -52)
+        assert abs(info["shift_tries"][0] - want) <= 8 * U * want
+
+
+# --------------------------------------------------------------------------
+# the stopping quantity and the metrics at exact non-zero values
+# --------------------------------------------------------------------------
+def test_fro_distance_exact_nonzero():
+    # X - I = [[1, 2], [2, 4]]: squares sum to 25
+    assert O.fro_dist_identity(np.array([[2.0, 2.0], [2.0, 5.0]])) == 5.0
+    assert O.fro_dist_identity(np.diag([4.0, 1.0])) == 3.0
+    assert O.fro_dist_identity(np.zeros((3, 3))) == math.sqrt(3.0)
+
+
+def test_metrics_exact_nonzero():
+    A = np.array([[6.0], [8.0]])
+    Q = np.array([[1.0], [0.0]])
+    R = np.array([[6.0]])
+    assert O.rrr(A, Q, R) == 8.0 / 10.0              # ||[0, 8]|| / ||[6, 8]||
+    assert O.rcr(A, R) == 64.0 / 100.0               # |100 - 36| / 10^2
+    assert O.loo(np.array([[3.0, 0.0], [0.0, 2.0]])) == math.sqrt(64.0 + 9.0)
+
+
+def test_stop_test_is_strict_on_the_frobenius_distance():
+    """A = [2 h1, h2] / 8 (m = 64): X = diag(4, 1), ||X - I||_F = 3 exactly.
+    With tol = 3.5 Algorithm 1 stops before any pass (Q = A, R = I); with
+    tol = 3 the test ||X - I||_F < tol fails and one pass gives the exact QR
+    R = diag(2, 1), Q = [h1, h2] / 8."""
+    H = S.hadamard(64)
+    A = np.stack([2.0 * H[:, 0], H[:, 1]], axis=1) / 8.0
+    kw = dict(first_pass_shift=0, min_passes=0)
+    Q, R, info = O.orth(A, tol=3.5, **kw)
+    assert info["passes"] == 0 and info["orth_fro"] == 3.0 and info["status"] == O.OK
+    assert np.array_equal(Q, A) and np.array_equal(R, np.eye(2))
+    Q, R, info = O.orth(A, tol=3.0, **kw)
+    assert info["passes"] == 1 and info["orth_fro"] == 0.0
+    assert np.array_equal(R, np.diag([2.0, 1.0])) and np.array_equal(Q, H[:, :2] / 8.0)
+
+
+def test_append_entry_case_projects_once():
+    """A_in = Q_in C + H_p / 2^k with Q_in = H_q / 2^k: the initial Schur
+    complement is I exactly although B~ = C is not zero.  Prop. 2.1's
+    projection must still be applied: one pass gives Q = H_p / 2^k, B = C,
+    R = I, all exact, and the full basis is orthonormal."""
+    k, q, p = 4, 12, 5
+    H = S.hadamard(4 ** k)
+    Qin = H[:, :q] / 2.0 ** k
+    C = np.random.default_rng(17).integers(-3, 4, size=(q, p)).astype(np.float64)
+    W = Qin @ C + H[:, q:q + p] / 2.0 ** k
+    Bt, G = O.gram_append(Qin, W)
+    assert np.array_equal(Bt, C)
+    assert np.array_equal(O.schur(G, Bt), np.eye(p))
+    Qo, Ro, info = O.append(Qin, np.eye(q), W)
+    assert info["status"] == O.OK and info["passes"] == 1
+    assert np.array_equal(Qo[:, q:], H[:, q:q + p] / 2.0 ** k)
+    assert np.array_equal(Ro[:q, q:], C)
+    assert np.array_equal(Ro[q:, q:], np.eye(p))
+    assert O.loo(Qo) == 0.0
+
+
+# --------------------------------------------------------------------------
+# the Cholesky QR variants of Sec. 3.1 and Fig. 1's robustness pattern
+# --------------------------------------------------------------------------
+def test_fig1_pattern_all_variants():
+    """300 x 10 inputs, kappa = 10^0 .. 10^20 (Sec. 3.2): plain CholQR loses
+    orthogonality as kappa^2 u and CholQR/CholQR2 cannot factor the Gramian
+    above about 1/sqrt(u) (the paper: kappa >= 1e8); sCholQR3 holds for
+    moderate kappa; Algorithm 1 (rsCholQR), isCholQR and CholQR3 reach the
+    stopping tolerance up to kappa = 1e20."""
+    m, n = GOLDEN["fig1_shape"]["m"], GOLDEN["fig1_shape"]["n"]
+    tol = GOLDEN["stop_tol"]["value"]
+    limit = GOLDEN["cholqr2_fails_above_kappa"]["value"]
+    for e in range(0, 21):
+        kappa = 10.0 ** e
+        A = S.test_matrix(m, n, kappa, seed=(6,))
+        res = {v: O.orth(A, **kw) for v, kw in O.VARIANTS.items()}
+        loo = {v: O.loo(r[0]) for v, r in res.items()}
+        st = {v: r[2]["status"] for v, r in res.items()}
+        for v in ("rsCholQR", "isCholQR", "CholQR3"):
+            assert st[v] == O.OK and loo[v] <= tol, (v, e)
+        if kappa <= 1e12:
+            assert st["sCholQR3"] == O.OK and loo["sCholQR3"] <= tol, e
+        if kappa <= 1e7:
+            assert st["CholQR2"] == O.OK and loo["CholQR2"] <= tol, e
+        if kappa >= 100 * limit:
+            assert st["CholQR"] == st["CholQR2"] == O.BREAKDOWN, e
+        if 1e3 <= kappa <= 1e8:
+            # one plain pass: LOO of the order kappa^2 u
+            assert 1e-3 * kappa ** 2 * U <= loo["CholQR"] <= 1e3 * kappa ** 2 * U, e
+        # a plain variant never shifts; CholQR2 makes exactly its two passes
+        assert all(s == 0.0 for s in res["CholQR2"][2]["sigma"])
+        if st["CholQR2"] == O.OK:
+            assert res["CholQR2"][2]["passes"] == 2
+
+
+def test_isCholQR_reuses_the_input_shift():
+    """isCholQR computes sigma once from X_0 = A^T A and reapplies it on every
+    breakdown: with A scaled by 2^20 (||X_0|| = 2^40) the shift on every
+    shifted pass equals the one from the input Gramian."""
+    A = S.test_matrix(300, 10, 1e16, seed=(6,)) * 2.0 ** 20
+    _, _, info = O.orth(A, **O.VARIANTS["isCholQR"])
+    lam = O.lambda_max(O.gram(A))
+    want = O.shift_orth(300, 10, lam)
+    shifted = [s for s in info["sigma"] if s > 0.0]
+    assert shifted and all(s == want for s in shifted)
+    assert info["shift_tries"] == shifted
+
+
+# --------------------------------------------------------------------------
 # planted mistakes: each plausible slip in the oracle must fail a pin above
 # --------------------------------------------------------------------------
 def _fails(pin, *args):
@@ -546,3 +768,64 @@ def test_planted_mixed_mistakes_are_caught(monkeypatch):
         with monkeypatch.context() as mp:
             mp.setattr(C, name, bad)
             assert _fails(p), name
+
+
+# Source-level mutants of the oracle: each replaces one exact fragment of
+# oracle/cholqr.py, is loaded as a separate module, and must fail the pin
+# named beside it.  (Dropping the 2u floor after a x10 step is not among
+# them: the shift already starts at or above 2u, so ten times it is at least
+# 20u and that floor can never bind -- an equivalent mutant that no input can
+# tell apart; the floor on the first shift is pinned by
+# test_escalation_floor.)
+_MUTANTS = [
+    ("x2 escalation", "sigma = max(10.0 * sigma, 2.0 * u)",
+     "sigma = max(2.0 * sigma, 2.0 * u)", "test_escalation_sequence_exact"),
+    ("x100 escalation", "sigma = max(10.0 * sigma, 2.0 * u)",
+     "sigma = max(100.0 * sigma, 2.0 * u)", "test_escalation_sequence_exact"),
+    ("first shift not floored", "sigma = max(sigma0, 2.0 * u)", "sigma = sigma0",
+     "test_escalation_floor"),
+    ("cap raised by 5", "if attempts > max_escalations:", "if attempts > max_escalations + 5:",
+     "test_escalation_cap"),
+    ("cap raised by 5 (driver)", "if attempts > max_escalations:",
+     "if attempts > max_escalations + 5:", "test_orth_breakdown_at_the_escalation_cap"),
+    ("squared stopping distance",
+     'return float(np.linalg.norm(X - np.eye(X.shape[0]), "fro"))',
+     'return float(np.linalg.norm(X - np.eye(X.shape[0]), "fro")) ** 2',
+     "test_stop_test_is_strict_on_the_frobenius_distance"),
+    ("squared stopping distance (unit)",
+     'return float(np.linalg.norm(X - np.eye(X.shape[0]), "fro"))',
+     'return float(np.linalg.norm(X - np.eye(X.shape[0]), "fro")) ** 2',
+     "test_fro_distance_exact_nonzero"),
+    ("non-strict stopping test", 'passes >= o["min_passes"] and err < o["tol"]',
+     'passes >= o["min_passes"] and err <= o["tol"]',
+     "test_stop_test_is_strict_on_the_frobenius_distance"),
+    ("squared RRR", "return float(np.linalg.norm(A - Q @ R) / np.linalg.norm(A))",
+     "return float(np.linalg.norm(A - Q @ R) / np.linalg.norm(A)) ** 2",
+     "test_metrics_exact_nonzero"),
+    ("RCR over ||A||", "/ np.linalg.norm(A) ** 2)", "/ np.linalg.norm(A))",
+     "test_metrics_exact_nonzero"),
+    ("append stops before projecting", 'if passes >= 1 and err < o["tol"]:',
+     'if err < o["tol"]:', "test_append_entry_case_projects_once"),
+    ("append shift dimension ignored", 'd = (q, p, q + p)[int(o["append_shift_dim"])]',
+     "d = q", "test_append_first_shift_dimension"),
+    ("isCholQR recomputes its shift", "sigma = sigma_fixed",
+     'sigma = shift_orth(m, n, lambda_max(X, o["power_steps"]), u)',
+     "test_isCholQR_reuses_the_input_shift"),
+    ("plain variants shift on breakdown", "shifted = not ok and policy != NO_SHIFT",
+     "shifted = not ok", "test_fig1_pattern_all_variants"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", _MUTANTS, ids=[m[0] for m in _MUTANTS])
+def test_source_mutant_is_caught(name, old, new, pin, monkeypatch):
+    import types
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "oracle", "cholqr.py")
+    src = open(path).read()
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+    pin_fn = globals()[pin]
+    assert not _fails(pin_fn)                      # the pin holds on the oracle
+    monkeypatch.setitem(globals(), "O", mod)
+    assert _fails(pin_fn), name
