@@ -59,6 +59,25 @@ typedef struct sqr_opts {
                                all-ones vector, 1..1000, default 30 (for
                                p <= 64 the same iterate X^s 1 is formed from
                                powers of X by repeated squaring)              */
+  int32_t shift_policy;     /* sqr_orth only (sqr_append always follows
+                               Algorithm 2), the variants of Sec. 3.1:
+                               0 = Algorithm 1: on a breakdown the shift is
+                                   recomputed from the current Gramian (x10
+                                   escalation if the shifted factorisation
+                                   still breaks down), default;
+                               1 = no shift: a breakdown ends the call with
+                                   SQR_BREAKDOWN, and a shifted first pass
+                                   does not escalate (CholQR: max_iter = 1,
+                                   CholQR2: 2, shiftedCholeskyQR3: 3 with
+                                   first_pass_shift = 1);
+                               2 = isCholQR: one shift, computed from the
+                                   input Gramian (||A||^2), is used for every
+                                   breakdown; if it fails, SQR_BREAKDOWN.
+                               1 and 2 need precision = 0.                   */
+  int32_t append_shift_dim; /* sqr_append: the width d in Algorithm 2's first
+                               shift 11 (m d + d (d+1)) u ||X||: 0 = q, the
+                               basis width, as printed (default); 1 = p, the
+                               block width; 2 = q + p                         */
 } sqr_opts;
 
 /* Outcome of one call (host struct). */
@@ -99,6 +118,10 @@ void sqr_default_opts(sqr_opts* o);
  *
  * Ownership: A, Q and R are borrowed and must stay allocated until the work
  * enqueued on `stream` completes.  The handle owns only its workspace.
+ * Streams: a later call on the handle may use another stream; it first makes
+ * that stream wait for all work of the handle's previous call (an event),
+ * so the calls of one handle are always ordered.  A handle must not be used
+ * by two host threads at once.
  * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
  * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT (also for
  * precision 1 with n > 256), SQR_EHIP; all
@@ -115,7 +138,9 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
  * p.  On any non-zero status n is unchanged (the reserved columns may hold
  * partial results).  W is read only.  Always waits for the outcome, as
  * sqr_orth does with a non-NULL info (the new width depends on it); `info`
- * may be NULL.
+ * may be NULL.  At least one pass runs, so the projection of Prop. 2.1 is
+ * applied even when the initial Schur complement already passes the
+ * stopping test (W = Q_in C + H, H orthonormal and orthogonal to Q_in).
  * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^27, n + p > cap,
  * n + p > m).
  */

@@ -24,7 +24,19 @@ class SqrOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("first_pass_shift", ctypes.c_int32),
                 ("min_passes", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("unit_roundoff", ctypes.c_double),
-                ("max_escalations", ctypes.c_int32), ("power_steps", ctypes.c_int32)]
+                ("max_escalations", ctypes.c_int32), ("power_steps", ctypes.c_int32),
+                ("shift_policy", ctypes.c_int32), ("append_shift_dim", ctypes.c_int32)]
+
+#: option sets of the Cholesky QR variants of Sec. 3.1 (shift_policy 0:
+#: Algorithm 1's recomputed shift, 1: none, 2: isCholQR's fixed shift)
+VARIANTS = {
+    "CholQR": dict(first_pass_shift=0, min_passes=1, max_iter=1, shift_policy=1),
+    "CholQR2": dict(first_pass_shift=0, min_passes=2, max_iter=2, shift_policy=1),
+    "sCholQR3": dict(first_pass_shift=1, min_passes=3, max_iter=3, shift_policy=1),
+    "isCholQR": dict(first_pass_shift=0, min_passes=0, max_iter=10, shift_policy=2),
+    "rsCholQR": dict(first_pass_shift=0, min_passes=0, max_iter=10, shift_policy=0),
+    "CholQR3": dict(first_pass_shift=1, min_passes=3, max_iter=10, shift_policy=0),
+}
 
 
 class SqrInfo(ctypes.Structure):
@@ -124,17 +136,35 @@ class Basis:
             sqr_free(self)
 
 
+def _check_matrix(name: str, t: torch.Tensor, rows: int, min_cols: int, device) -> None:
+    """Shape and device of a caller buffer, before the library sees only its
+    pointer and leading dimension."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a matrix")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.shape[0] != rows or t.shape[1] < min_cols:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({rows}, >= {min_cols})")
+
+
 def sqr_orth(A: torch.Tensor, cap: int | None = None, opts: SqrOpts | None = None,
              Q: torch.Tensor | None = None, R: torch.Tensor | None = None,
              stream=None, sync: bool = True):
     """Q R = A (Algorithm 1 with the CholQR3 start).  Returns (Basis, info
-    dict or None); raises on usage errors (negative codes)."""
+    dict or None); raises ValueError on inconsistent shapes or devices and
+    RuntimeError on other usage errors (negative codes)."""
+    if A.dim() != 2:
+        raise ValueError("A must be a matrix")
     m, n = A.shape
     cap = n if cap is None else cap
+    if cap < n:
+        raise ValueError(f"cap = {cap} is below n = {n}")
     if Q is None:
         Q = colmajor(m, cap, device=A.device)
     if R is None:
         R = colmajor(cap, cap, device=A.device)
+    _check_matrix("Q", Q, m, cap, A.device)
+    _check_matrix("R", R, cap, cap, A.device)
     h = ctypes.c_void_p()
     info = SqrInfo()
     rc = lib.sqr_orth(ctypes.byref(h), ctypes.byref(opts) if opts is not None else None,
@@ -148,7 +178,9 @@ def sqr_orth(A: torch.Tensor, cap: int | None = None, opts: SqrOpts | None = Non
 
 def sqr_append(b: Basis, W: torch.Tensor, stream=None) -> dict:
     """Algorithm 2: append the columns of W to the basis.  Returns the info
-    dict; raises on usage errors."""
+    dict; raises ValueError on a W of the wrong height or device and
+    RuntimeError on other usage errors."""
+    _check_matrix("W", W, b.m, 1, b.Q.device)
     info = SqrInfo()
     rc = lib.sqr_append(b.handle, W.data_ptr(), W.shape[1], _ld(W), _stream(stream),
                         ctypes.byref(info))

@@ -44,11 +44,13 @@ size_t g_small_lds = kSmallLdsBytes;
 
 // ---- measurement records (sqr_prof.h) ----
 struct ProfRec { hipEvent_t e0, e1; int kind; double bytes; int64_t call; int phase; int real; };
-std::vector<ProfRec> g_prof;
-std::vector<hipEvent_t> g_event_pool;
-bool g_prof_on = false;
+std::vector<ProfRec> g_prof;             // guarded by g_prof_mu
+std::vector<hipEvent_t> g_event_pool;    // guarded by g_prof_mu
+std::mutex g_prof_mu;
+std::atomic<bool> g_prof_on{false};
 std::atomic<int64_t> g_call_id{0};
 
+// Caller holds g_prof_mu.
 hipEvent_t take_event() {
   if (g_event_pool.empty()) {
     hipEvent_t e;
@@ -63,8 +65,29 @@ hipEvent_t take_event() {
 // Mark the records of call `id`: launches of passes after the last executed
 // one were no-ops of a finished call.
 void prof_finalize(int64_t id, int passes) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (ProfRec& r : g_prof)
     if (r.call == id && r.real < 0) r.real = (r.phase <= passes) ? 1 : 0;
+}
+
+// Event pair around the launches of one streaming step (when recording).
+ProfRec prof_begin(int kind, double bytes, int64_t call, int phase, hipStream_t s) {
+  ProfRec rec{};
+  if (!g_prof_on) return rec;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    rec.e0 = take_event();
+    rec.e1 = take_event();
+  }
+  rec.kind = kind; rec.bytes = bytes; rec.call = call; rec.phase = phase; rec.real = -1;
+  if (rec.e0) (void)hipEventRecord(rec.e0, s);
+  return rec;
+}
+void prof_end(const ProfRec& rec, hipStream_t s) {
+  if (!rec.e0 || !rec.e1) return;
+  (void)hipEventRecord(rec.e1, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(rec);
 }
 
 // ---- workspace pool: device buffers (and the pinned state) of freed or
@@ -121,6 +144,8 @@ struct sqr_basis {
   sqr_opts opts;
   int device = 0;
   hipStream_t stream = nullptr;      // stream of the last call
+  bool used = false;                 // a call has been enqueued on `stream`
+  hipEvent_t order_ev = nullptr;     // orders a call after the previous one
   int64_t call_id = 0;               // id of the last call (measurement records)
   size_t ws_bytes = 0;
   int slots = 0;                     // partial-Gram slots (workgroups of block_pass)
@@ -200,9 +225,10 @@ size_t block_lds_bytes(const Variant& v, bool apply) {
               (apply ? (size_t)v.nt * v.wpt * 256 + 256 : 0));
 }
 
-bool g_attr_done = false;
-void set_kernel_attributes() {
-  if (g_attr_done) return;
+// Kernel attributes and occupancies, once per process (std::call_once: the
+// serving loop calls the library from several threads at once).
+std::once_flag g_attr_once;
+void set_kernel_attributes_once() {
   for (const Variant& v : kVariants) {
     (void)hipFuncSetAttribute((const void*)v.gram, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     (void)hipFuncSetAttribute((const void*)v.apply, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
@@ -281,8 +307,8 @@ void set_kernel_attributes() {
       n = 1;
     g_narrow_occ[ap] = n;
   }
-  g_attr_done = true;
 }
+void set_kernel_attributes() { std::call_once(g_attr_once, set_kernel_attributes_once); }
 
 // Worst-case sizes over every call the handle can make (q + p <= cap).
 int64_t worst_total_len(int64_t cap) {
@@ -375,18 +401,9 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     // launches between one pair of profiling events (the mixed form's two
     // Gramian variants count as one launch: one of them exits at once)
     auto timed = [&](int kind, double bytes, auto&& enqueue) {
-      ProfRec rec{};
-      if (g_prof_on) {
-        rec.e0 = take_event(); rec.e1 = take_event();
-        rec.kind = kind; rec.bytes = bytes;
-        rec.call = b->call_id; rec.phase = phase; rec.real = -1;
-        if (rec.e0) (void)hipEventRecord(rec.e0, s);
-      }
+      const ProfRec rec = prof_begin(kind, bytes, b->call_id, phase, s);
       if (!enqueue()) return false;
-      if (g_prof_on && rec.e0 && rec.e1) {
-        (void)hipEventRecord(rec.e1, s);
-        g_prof.push_back(rec);
-      }
+      prof_end(rec, s);
       return true;
     };
     if (apply) {
@@ -434,21 +451,12 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.passes = &b->ctrl->passes;
     w.copy_if_done = (phase == 1);
     void* args[] = {&w};
-    ProfRec rec{};
-    if (g_prof_on) {
-      rec.e0 = take_event(); rec.e1 = take_event();
-      rec.kind = apply ? 1 : 0;
-      rec.bytes = 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0);
-      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
-      if (rec.e0) (void)hipEventRecord(rec.e0, s);
-    }
+    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
+                                   b->call_id, phase, s);
     if (hipLaunchKernel((const void*)kNarrow[apply ? 1 : 0], dim3((unsigned)nwg), dim3(kThreads), args, 0, s) !=
         hipSuccess)
       return SQR_EHIP;
-    if (g_prof_on && rec.e0 && rec.e1) {
-      (void)hipEventRecord(rec.e1, s);
-      g_prof.push_back(rec);
-    }
+    prof_end(rec, s);
   } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
     // precision from pass 1 on; the one that does not match the device's
@@ -470,14 +478,8 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.passes = &b->ctrl->passes;
     w.copy_if_done = (phase == 1);
     void* args[] = {&w};
-    ProfRec rec{};
-    if (g_prof_on) {
-      rec.e0 = take_event(); rec.e1 = take_event();
-      rec.kind = apply ? 1 : 0;
-      rec.bytes = 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0);
-      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
-      if (rec.e0) (void)hipEventRecord(rec.e0, s);
-    }
+    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
+                                   b->call_id, phase, s);
     for (int g32 = mixed ? 1 : 0; g32 >= 0; --g32) {
       // phase 0 of the mixed form is an FP32 Gramian; later phases follow the
       // device (ctrl->gram32); FP64 calls launch the FP64 variant only
@@ -488,10 +490,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
                           wide_lds_bytes((int)P, apply), s) != hipSuccess)
         return SQR_EHIP;
     }
-    if (g_prof_on && rec.e0 && rec.e1) {
-      (void)hipEventRecord(rec.e1, s);
-      g_prof.push_back(rec);
-    }
+    prof_end(rec, s);
   } else {
   // One grid size for every block of the pass (the slots are reduced
   // together): resident workgroups of the most demanding block's variant,
@@ -526,21 +525,12 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     const int ks = (int)round4(a.n1) + a.n2;   // columns of S with the padding
     const Variant* v = pick_variant((ks + 15) / 16);
     void* args[] = {&a};
-    ProfRec rec{};
-    if (g_prof_on) {
-      rec.e0 = take_event(); rec.e1 = take_event();
-      rec.kind = apply ? 1 : 0;
-      rec.bytes = 8.0 * (double)b->m * (double)(ks + (apply ? 2 : 1) * a.pb);
-      rec.call = b->call_id; rec.phase = phase; rec.real = -1;
-      if (rec.e0) (void)hipEventRecord(rec.e0, s);
-    }
+    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)(ks + (apply ? 2 : 1) * a.pb),
+                                   b->call_id, phase, s);
     if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
                         dim3(kThreads), args, block_lds_bytes(*v, apply), s) != hipSuccess)
       return SQR_EHIP;
-    if (g_prof_on && rec.e0 && rec.e1) {
-      (void)hipEventRecord(rec.e1, s);
-      g_prof.push_back(rec);
-    }
+    prof_end(rec, s);
   }
   }
   // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
@@ -559,6 +549,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
   k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
   k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+  k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
   k.mixed = mixed ? 1 : 0;
   const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
   const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
@@ -614,6 +605,19 @@ void fill_info(const Ctrl* c, sqr_info* info) {
 // Run one call.  sync: enqueue `spec` passes, then add passes one by one while
 // the device reports neither convergence nor failure.
 int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
+  if (b->used && s != b->stream) {
+    // Kernels of the previous call (no-op launches of a finished call among
+    // them) may still be queued on its stream and read the control block
+    // that this call resets: this stream waits for all of them.
+    if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
+      b->order_ev = nullptr;
+      return SQR_EHIP;
+    }
+    if (hipEventRecord(b->order_ev, b->stream) != hipSuccess ||
+        hipStreamWaitEvent(s, b->order_ev, 0) != hipSuccess)
+      return SQR_EHIP;
+  }
+  b->used = true;
   b->stream = s;
   b->call_id = ++g_call_id;
   int rc = launch_gram(b, c, 0, s);
@@ -636,7 +640,8 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
 bool opts_ok(const sqr_opts& o) {
   return (o.precision == 0 || o.precision == 1) && o.max_iter >= 1 && o.max_iter <= 64 && o.min_passes >= 0 &&
          o.tol > 0.0 && o.unit_roundoff > 0.0 && o.max_escalations >= 0 &&
-         o.power_steps >= 1 && o.power_steps <= 1000;
+         o.power_steps >= 1 && o.power_steps <= 1000 && o.shift_policy >= 0 && o.shift_policy <= 2 &&
+         (o.shift_policy == 0 || o.precision == 0) && o.append_shift_dim >= 0 && o.append_shift_dim <= 2;
 }
 
 }  // namespace
@@ -653,6 +658,8 @@ void sqr_default_opts(sqr_opts* o) {
   o->unit_roundoff = 1.1102230246251565e-16;  // 2^-53
   o->max_escalations = 32;
   o->power_steps = 30;
+  o->shift_policy = 0;
+  o->append_shift_dim = 0;
 }
 
 int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
@@ -722,6 +729,7 @@ int64_t sqr_cols(const sqr_basis* b) { return b ? b->n : 0; }
 void sqr_free(sqr_basis* b) {
   if (!b) return;
   (void)sqr_park(b);
+  if (b->order_ev) (void)hipEventDestroy(b->order_ev);
   delete b;
 }
 
@@ -744,6 +752,7 @@ int sqr_park(sqr_basis* b) {
 }
 
 void sqr_prof_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (ProfRec& r : g_prof) { g_event_pool.push_back(r.e0); g_event_pool.push_back(r.e1); }
   g_prof.clear();
   g_prof_on = on != 0;
@@ -752,6 +761,7 @@ void sqr_prof_enable(int on) {
 int sqr_prof_read(sqr_prof* out) {
   if (!out) return SQR_ENULL;
   memset(out, 0, sizeof(*out));
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   int rc = SQR_OK;
   for (ProfRec& r : g_prof) {
     if (hipEventSynchronize(r.e1) != hipSuccess) { rc = SQR_EHIP; continue; }

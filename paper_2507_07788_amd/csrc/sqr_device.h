@@ -23,6 +23,7 @@ struct Ctrl {
   int32_t pad[2];
   double orth_fro;        // last ||X - I||_F
   double sigma[16];       // shift of each pass (0 = unshifted)
+  double sigma_fixed;     // isCholQR: the shift of the input Gramian
   int64_t stamp;          // host copy only: call id * 256 + phase of the last
                           // small_step that published this state
 };
@@ -82,6 +83,8 @@ struct SmallArgs {
   int64_t stamp_base;    // call id * 256
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
+  int32_t shift_policy;  // orth: 0 recompute (Algorithm 1), 1 none, 2 fixed
+  int32_t shift_dim;     // append: first shift with 0 q, 1 p, 2 q + p
   double tol, u;
   int32_t mixed;         // orth in the mixed FP32/FP64 form
   int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X;

@@ -1432,6 +1432,240 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
       wg_sync(lo);
     }
   }
+  // ||X||_2 by power iteration from the all-ones vector (D6 of the readings;
+  // Appendix A asks only for a rough estimate).  Every thread calls it and
+  // receives the estimate.  On a copy of X in LDS when only M lives there: M
+  // is rebuilt from X after each use.
+  auto xnorm = [&]() -> double {
+    const double* Xs = X;
+    if (a.lds_matrices == 2) {
+      fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
+      Xs = M;
+    }
+    wg_sync(lo);   // X (or its copy) is complete before any wave reads it
+    // X is symmetric (mirrored from its upper triangle), so (X v)_i is read
+    // along column i: X[j p + i] over j, coalesced across rows i.
+    double lam = 0.0;
+    if (p <= 16) {
+      // One wave, in registers: X (zero-padded to 16 x 16) is held in the
+      // MFMA result layout, reg r of lane (x, g) = X[g + 4r][x].  X is
+      // symmetric, so that layout is also the A and B operand layout of a
+      // product with X: X^2 is four MFMAs on the registers, and so are
+      // X^4, X^8, ...  The steps of the iteration are applied as
+      // v = X^s 1 / ||X^s 1||: the first step X 1 explicitly (X 1 = 0 ends
+      // the iteration, as in the step-by-step form), then X^(s-1) as the
+      // product of the powers X^(2^k) for the set bits k of s - 1 (each
+      // power scaled to unit Frobenius norm; scaling only changes the
+      // length of the iterate): the same vector as s normalised steps.  The vector is kept as column 0 of a 16 x 16
+      // operand, which the MFMA result layout also matches.
+      if (tid < 64) {
+        const int x = tid & 15, g = tid >> 4;
+        auto wsum = [](double t) {
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+          return t;
+        };
+        auto fro = [&](const d4& t) {
+          return sqrt(wsum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3]));
+        };
+        auto prod = [&](const d4& pa, const d4& pb) {
+          d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = mfma(pa[r], pb[r], acc);
+          return acc;
+        };
+        d4 xm;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          xm[r] = (g + 4 * r < p && x < p) ? Xs[(int64_t)(g + 4 * r) * p + x] : 0.0;
+        d4 vv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) vv[r] = (x == 0 && g + 4 * r < p) ? 1.0 : 0.0;
+        // the first step explicitly: X 1 = 0 ends the iteration with 0
+        vv = prod(xm, vv);
+        const double n1 = fro(vv);
+        double lw;
+        if (!(n1 > 0.0) || !isfinite(n1)) {
+          lw = isfinite(n1) ? 0.0 : __builtin_nan("");
+        } else {
+          vv = vv * (1.0 / n1);
+          const int rest = a.power_steps - 1;
+          d4 pw = xm * (1.0 / fro(xm));   // X^(2^k), scaled
+          for (int k = 0; (rest >> k) != 0; ++k) {
+            if ((rest >> k) & 1) vv = prod(pw, vv);
+            if ((rest >> (k + 1)) != 0) {
+              pw = prod(pw, pw);
+              const double fp = fro(pw);
+              pw = pw * (1.0 / fp);
+            }
+          }
+          const double nrm = fro(vv);
+          if (!(nrm > 0.0) || !isfinite(nrm)) {
+            lw = isfinite(nrm) ? 0.0 : __builtin_nan("");
+          } else {
+            vv = vv * (1.0 / nrm);
+            const d4 xv = prod(xm, vv);
+            lw = fabs(wsum(vv[0] * xv[0] + vv[1] * xv[1] + vv[2] * xv[2] + vv[3] * xv[3]));
+          }
+        }
+        if (tid == 0) w[0] = lw;
+      }
+      wg_sync(lo);
+      lam = w[0];
+    } else if (p <= 64) {
+      // Four waves, the same power scheme on 16 x 16 tiles (nt x nt of
+      // them, zero-padded): each power X^(2^k) is formed on MFMA from the
+      // previous one (read along columns, which symmetry allows), scaled
+      // to unit Frobenius norm and stored row-major in M; the iterate
+      // (column 0 of a 16 nt x 16 operand, in v), after the explicit first
+      // step X 1, is multiplied by each power whose bit of s - 1 is set as
+      // soon as it is formed (powers of X commute).  X itself stays intact
+      // for the final Rayleigh quotient.
+      const int nt = (p + 15) >> 4;
+      const int wv = tid >> 6, x = tid & 15, g = (tid >> 4) & 3;
+      const double* src = Xs;   // the current power (X first)
+      auto opnd = [&](const double* P, int r, int c) {   // P[r][c], zero padding
+        return (r < p && c < p) ? P[(int64_t)r * p + c] : 0.0;
+      };
+      // v <- P v for the current power P (tile row I = wave), in place
+      auto apply_v = [&](const double* P) {
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        if (wv < nt) {
+          for (int K = 0; K < nt; ++K)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const int kk = 16 * K + 4 * s4 + g;
+              const double av = opnd(P, kk, 16 * wv + x);            // P[16wv + x][kk]
+              const double bv = (x == 0 && kk < p) ? v[kk] : 0.0;
+              acc = mfma(av, bv, acc);
+            }
+        }
+        wg_sync(lo);   // every wave has read v
+        if (wv < nt && x == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * wv + g + 4 * r;
+            if (row < p) v[row] = acc[r];
+          }
+        }
+        wg_sync(lo);
+      };
+      for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0;
+      // ||X||_F (scaling only changes lengths)
+      double part = 0.0;
+      for (int e = tid; e < p * p; e += kSmallThreads) part += Xs[e] * Xs[e];
+      const double f = sqrt(block_sum(part, red, lo));
+      // the first step explicitly: X 1 = 0 ends the iteration with 0
+      apply_v(src);
+      double n1 = 0.0;
+      for (int i = tid; i < p; i += kSmallThreads) n1 += v[i] * v[i];
+      n1 = sqrt(block_sum(n1, red, lo));
+      if (!(n1 > 0.0) || !isfinite(n1) || !isfinite(f)) {
+        lam = (isfinite(n1) && isfinite(f)) ? 0.0 : __builtin_nan("");
+      } else {
+        for (int i = tid; i < p; i += kSmallThreads) v[i] = v[i] / n1;
+        wg_sync(lo);
+        const int rest = a.power_steps - 1;
+        double scale = 1.0 / f;   // the current power is scale * src
+        for (int k = 0; (rest >> k) != 0; ++k) {
+          if ((rest >> k) & 1) apply_v(src);
+          if ((rest >> (k + 1)) == 0) break;
+          // next power: (scale src)^2, tiles t = wv, wv + 4, ...
+          d4 nxt[4];
+          double sq = 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            nxt[u] = d4{0.0, 0.0, 0.0, 0.0};
+            const int t = wv + kSmallWaves * u;
+            if (t < nt * nt) {
+              const int I = t / nt, J = t % nt;
+              for (int K = 0; K < nt; ++K)
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                  const int kk = 16 * K + 4 * s4 + g;
+                  nxt[u] = mfma(opnd(src, kk, 16 * I + x) * scale, opnd(src, kk, 16 * J + x) * scale, nxt[u]);
+                }
+#pragma unroll
+              for (int r = 0; r < 4; ++r) sq += nxt[u][r] * nxt[u][r];
+            }
+          }
+          const double fp = sqrt(block_sum(sq, red, lo));   // also: all reads of src done
+          scale = 1.0 / fp;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = wv + kSmallWaves * u;
+            if (t < nt * nt) {
+              const int I = t / nt, J = t % nt;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + g + 4 * r, col = 16 * J + x;
+                if (row < p && col < p) M[(int64_t)row * p + col] = nxt[u][r];
+              }
+            }
+          }
+          src = M;
+          wg_sync(lo);
+        }
+        // lam = |v^T X v| / (v^T v) with X itself (not a copy that the
+        // powers may have overwritten)
+        double vv = 0.0;
+        for (int i = tid; i < p; i += kSmallThreads) vv += v[i] * v[i];
+        const double nv = sqrt(block_sum(vv, red, lo));
+        if (!(nv > 0.0) || !isfinite(nv)) {
+          lam = isfinite(nv) ? 0.0 : __builtin_nan("");
+        } else {
+          for (int i = tid; i < p; i += kSmallThreads) w[i] = v[i] / nv;
+          wg_sync(lo);
+          double rq = 0.0;
+          for (int i = tid; i < p; i += kSmallThreads) {
+            double t = 0.0;
+            for (int j = 0; j < p; ++j) t += X[(int64_t)j * p + i] * w[j];
+            rq += w[i] * t;
+          }
+          lam = fabs(block_sum(rq, red, lo));
+        }
+      }
+    } else {
+      // all waves: thread t takes row t mod p and one of H column ranges;
+      // the H partial sums of a row are added in range order
+      const int H = max(1, kSmallThreads / p);
+      for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
+      wg_sync(lo);
+      // returns w_i (thread i < p, else 0) with the partial sums in w[]
+      auto mv = [&]() {
+        for (int t0 = tid; t0 < p * H; t0 += kSmallThreads) {
+          const int i = t0 % p, h = t0 / p;
+          const int j0 = h * p / H, j1 = (h + 1) * p / H;
+          double t = 0.0;
+#pragma unroll 16
+          for (int j = j0; j < j1; ++j) t += Xs[(int64_t)j * p + i] * v[j];
+          w[h * p + i] = t;
+        }
+        wg_sync(lo);
+        double t = 0.0;
+        if (tid < p)
+          for (int h = 0; h < H; ++h) t += w[h * p + tid];
+        return t;
+      };
+      bool early = false;
+      for (int s = 0; s < a.power_steps; ++s) {
+        const double t = mv();
+        const double nrm = sqrt(block_sum(t * t, red, lo));
+        if (!(nrm > 0.0) || !isfinite(nrm)) {
+          lam = isfinite(nrm) ? nrm : __builtin_nan("");
+          early = true;
+          break;
+        }
+        if (tid < p) v[tid] = t / nrm;
+        wg_sync(lo);
+      }
+      if (!early) {
+        const double t = mv();
+        lam = fabs(block_sum(tid < p ? v[tid] * t : 0.0, red, lo));
+      }
+    }
+    return lam;
+  };
   // 3. ||X - I||_F.
   double part = 0.0;
   for (int i = tid >> 4; i < p; i += kSmallThreads / 16) {
@@ -1442,11 +1676,25 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     }
   }
   const double err = sqrt(block_sum(part, red, lo));
-  // 4. Stopping test (Algorithm 1 with the CholQR3 start; Algorithm 2).
+  // Shift policy of an orth call (appends always follow Algorithm 2):
+  // 0 Algorithm 1 (recomputed from the current X, x10 escalation), 1 none
+  // (a breakdown ends the call; a shifted first pass does not escalate),
+  // 2 isCholQR (one shift from the input Gramian, reapplied on breakdown).
+  const int pol = (a.mode == 0) ? a.shift_policy : 0;
+  const double mm = (double)a.m;
+  if (pol == 2 && ph0 && isfinite(err)) {
+    // ||X_0|| = ||A||^2: the one shift of the call
+    const double lam0 = xnorm();
+    if (tid == 0) c->sigma_fixed = fmax(11.0 * (mm * p + (double)p * (p + 1)) * a.u * lam0, 2.0 * a.u);
+  }
+  // 4. Stopping test (Algorithm 1 with the CholQR3 start; Algorithm 2, whose
+  //    first pass always runs: Prop. 2.1 forms the new columns by the
+  //    projection, and an initial X = I does not make B~ zero).
   int status = -1;
   if (!isfinite(err)) {
     status = 3;  // SQR_ENONFINITE
-  } else if ((a.mode == 0) ? (!cur32 && a.phase >= a.min_passes && err < a.tol) : (err < a.tol)) {
+  } else if ((a.mode == 0) ? (!cur32 && a.phase >= a.min_passes && err < a.tol)
+                           : (a.phase >= 1 && err < a.tol)) {
     status = 0;
   } else if (a.phase >= a.max_iter) {
     status = 1;  // SQR_NOT_CONVERGED
@@ -1478,249 +1726,28 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     if (need_shift) {
       need_shift = false;
       shifted = true;
-      // ||X||_2 by power iteration from the all-ones vector (on a copy of X in
-      // LDS when only M lives there: M is rebuilt from X below).
-      const double* Xs = X;
-      if (a.lds_matrices == 2) {
-        fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j]; });
-        Xs = M;
-      }
-      wg_sync(lo);   // X (or its copy) is complete before any wave reads it
-      // X is symmetric (mirrored from its upper triangle), so (X v)_i is read
-      // along column i: X[j p + i] over j, coalesced across rows i.
-      double lam = 0.0;
-      if (p <= 16) {
-        // One wave, in registers: X (zero-padded to 16 x 16) is held in the
-        // MFMA result layout, reg r of lane (x, g) = X[g + 4r][x].  X is
-        // symmetric, so that layout is also the A and B operand layout of a
-        // product with X: X^2 is four MFMAs on the registers, and so are
-        // X^4, X^8, ...  The steps of the iteration are applied as
-        // v = X^s 1 / ||X^s 1||: the first step X 1 explicitly (X 1 = 0 ends
-        // the iteration, as in the step-by-step form), then X^(s-1) as the
-        // product of the powers X^(2^k) for the set bits k of s - 1 (each
-        // power scaled to unit Frobenius norm; scaling only changes the
-        // length of the iterate): the same vector as s normalised steps.  The vector is kept as column 0 of a 16 x 16
-        // operand, which the MFMA result layout also matches.
-        if (tid < 64) {
-          const int x = tid & 15, g = tid >> 4;
-          auto wsum = [](double t) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-            return t;
-          };
-          auto fro = [&](const d4& t) {
-            return sqrt(wsum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3]));
-          };
-          auto prod = [&](const d4& pa, const d4& pb) {
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc = mfma(pa[r], pb[r], acc);
-            return acc;
-          };
-          d4 xm;
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            xm[r] = (g + 4 * r < p && x < p) ? Xs[(int64_t)(g + 4 * r) * p + x] : 0.0;
-          d4 vv;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) vv[r] = (x == 0 && g + 4 * r < p) ? 1.0 : 0.0;
-          // the first step explicitly: X 1 = 0 ends the iteration with 0
-          vv = prod(xm, vv);
-          const double n1 = fro(vv);
-          double lw;
-          if (!(n1 > 0.0) || !isfinite(n1)) {
-            lw = isfinite(n1) ? 0.0 : __builtin_nan("");
-          } else {
-            vv = vv * (1.0 / n1);
-            const int rest = a.power_steps - 1;
-            d4 pw = xm * (1.0 / fro(xm));   // X^(2^k), scaled
-            for (int k = 0; (rest >> k) != 0; ++k) {
-              if ((rest >> k) & 1) vv = prod(pw, vv);
-              if ((rest >> (k + 1)) != 0) {
-                pw = prod(pw, pw);
-                const double fp = fro(pw);
-                pw = pw * (1.0 / fp);
-              }
-            }
-            const double nrm = fro(vv);
-            if (!(nrm > 0.0) || !isfinite(nrm)) {
-              lw = isfinite(nrm) ? 0.0 : __builtin_nan("");
-            } else {
-              vv = vv * (1.0 / nrm);
-              const d4 xv = prod(xm, vv);
-              lw = fabs(wsum(vv[0] * xv[0] + vv[1] * xv[1] + vv[2] * xv[2] + vv[3] * xv[3]));
-            }
-          }
-          if (tid == 0) w[0] = lw;
-        }
-        wg_sync(lo);
-        lam = w[0];
-      } else if (p <= 64) {
-        // Four waves, the same power scheme on 16 x 16 tiles (nt x nt of
-        // them, zero-padded): each power X^(2^k) is formed on MFMA from the
-        // previous one (read along columns, which symmetry allows), scaled
-        // to unit Frobenius norm and stored row-major in M; the iterate
-        // (column 0 of a 16 nt x 16 operand, in v), after the explicit first
-        // step X 1, is multiplied by each power whose bit of s - 1 is set as
-        // soon as it is formed (powers of X commute).  X itself stays intact
-        // for the final Rayleigh quotient.
-        const int nt = (p + 15) >> 4;
-        const int wv = tid >> 6, x = tid & 15, g = (tid >> 4) & 3;
-        const double* src = Xs;   // the current power (X first)
-        auto opnd = [&](const double* P, int r, int c) {   // P[r][c], zero padding
-          return (r < p && c < p) ? P[(int64_t)r * p + c] : 0.0;
-        };
-        // v <- P v for the current power P (tile row I = wave), in place
-        auto apply_v = [&](const double* P) {
-          d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-          if (wv < nt) {
-            for (int K = 0; K < nt; ++K)
-#pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) {
-                const int kk = 16 * K + 4 * s4 + g;
-                const double av = opnd(P, kk, 16 * wv + x);            // P[16wv + x][kk]
-                const double bv = (x == 0 && kk < p) ? v[kk] : 0.0;
-                acc = mfma(av, bv, acc);
-              }
-          }
-          wg_sync(lo);   // every wave has read v
-          if (wv < nt && x == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = 16 * wv + g + 4 * r;
-              if (row < p) v[row] = acc[r];
-            }
-          }
-          wg_sync(lo);
-        };
-        for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0;
-        // ||X||_F (scaling only changes lengths)
-        double part = 0.0;
-        for (int e = tid; e < p * p; e += kSmallThreads) part += Xs[e] * Xs[e];
-        const double f = sqrt(block_sum(part, red, lo));
-        // the first step explicitly: X 1 = 0 ends the iteration with 0
-        apply_v(src);
-        double n1 = 0.0;
-        for (int i = tid; i < p; i += kSmallThreads) n1 += v[i] * v[i];
-        n1 = sqrt(block_sum(n1, red, lo));
-        if (!(n1 > 0.0) || !isfinite(n1) || !isfinite(f)) {
-          lam = (isfinite(n1) && isfinite(f)) ? 0.0 : __builtin_nan("");
-        } else {
-          for (int i = tid; i < p; i += kSmallThreads) v[i] = v[i] / n1;
-          wg_sync(lo);
-          const int rest = a.power_steps - 1;
-          double scale = 1.0 / f;   // the current power is scale * src
-          for (int k = 0; (rest >> k) != 0; ++k) {
-            if ((rest >> k) & 1) apply_v(src);
-            if ((rest >> (k + 1)) == 0) break;
-            // next power: (scale src)^2, tiles t = wv, wv + 4, ...
-            d4 nxt[4];
-            double sq = 0.0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              nxt[u] = d4{0.0, 0.0, 0.0, 0.0};
-              const int t = wv + kSmallWaves * u;
-              if (t < nt * nt) {
-                const int I = t / nt, J = t % nt;
-                for (int K = 0; K < nt; ++K)
-#pragma unroll
-                  for (int s4 = 0; s4 < 4; ++s4) {
-                    const int kk = 16 * K + 4 * s4 + g;
-                    nxt[u] = mfma(opnd(src, kk, 16 * I + x) * scale, opnd(src, kk, 16 * J + x) * scale, nxt[u]);
-                  }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sq += nxt[u][r] * nxt[u][r];
-              }
-            }
-            const double fp = sqrt(block_sum(sq, red, lo));   // also: all reads of src done
-            scale = 1.0 / fp;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int t = wv + kSmallWaves * u;
-              if (t < nt * nt) {
-                const int I = t / nt, J = t % nt;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int row = 16 * I + g + 4 * r, col = 16 * J + x;
-                  if (row < p && col < p) M[(int64_t)row * p + col] = nxt[u][r];
-                }
-              }
-            }
-            src = M;
-            wg_sync(lo);
-          }
-          // lam = |v^T X v| / (v^T v) with X itself (not a copy that the
-          // powers may have overwritten)
-          double vv = 0.0;
-          for (int i = tid; i < p; i += kSmallThreads) vv += v[i] * v[i];
-          const double nv = sqrt(block_sum(vv, red, lo));
-          if (!(nv > 0.0) || !isfinite(nv)) {
-            lam = isfinite(nv) ? 0.0 : __builtin_nan("");
-          } else {
-            for (int i = tid; i < p; i += kSmallThreads) w[i] = v[i] / nv;
-            wg_sync(lo);
-            double rq = 0.0;
-            for (int i = tid; i < p; i += kSmallThreads) {
-              double t = 0.0;
-              for (int j = 0; j < p; ++j) t += X[(int64_t)j * p + i] * w[j];
-              rq += w[i] * t;
-            }
-            lam = fabs(block_sum(rq, red, lo));
-          }
-        }
+      if (pol == 2) {
+        sigma = c->sigma_fixed;
       } else {
-        // all waves: thread t takes row t mod p and one of H column ranges;
-        // the H partial sums of a row are added in range order
-        const int H = max(1, kSmallThreads / p);
-        for (int i = tid; i < p; i += kSmallThreads) v[i] = 1.0 / sqrt((double)p);
-        wg_sync(lo);
-        // returns w_i (thread i < p, else 0) with the partial sums in w[]
-        auto mv = [&]() {
-          for (int t0 = tid; t0 < p * H; t0 += kSmallThreads) {
-            const int i = t0 % p, h = t0 / p;
-            const int j0 = h * p / H, j1 = (h + 1) * p / H;
-            double t = 0.0;
-  #pragma unroll 16
-            for (int j = j0; j < j1; ++j) t += Xs[(int64_t)j * p + i] * v[j];
-            w[h * p + i] = t;
-          }
-          wg_sync(lo);
-          double t = 0.0;
-          if (tid < p)
-            for (int h = 0; h < H; ++h) t += w[h * p + tid];
-          return t;
-        };
-        bool early = false;
-        for (int s = 0; s < a.power_steps; ++s) {
-          const double t = mv();
-          const double nrm = sqrt(block_sum(t * t, red, lo));
-          if (!(nrm > 0.0) || !isfinite(nrm)) {
-            lam = isfinite(nrm) ? nrm : __builtin_nan("");
-            early = true;
-            break;
-          }
-          if (tid < p) v[tid] = t / nrm;
-          wg_sync(lo);
-        }
-        if (!early) {
-          const double t = mv();
-          lam = fabs(block_sum(tid < p ? v[tid] * t : 0.0, red, lo));
-        }
+        const double lam = xnorm();
+        // Algorithm 1: the Gramian's own width; Algorithm 2: q as printed,
+        // or p, or q + p (option)
+        const double d = (a.mode == 0) ? p : (a.shift_dim == 0 ? q : (a.shift_dim == 1 ? p : q + p));
+        const double cnt = mm * d + d * (d + 1.0);
+        sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
+                      : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
       }
-      const double mm = (double)a.m;
-      const double cnt = (a.mode == 0) ? (mm * p + (double)p * (p + 1))
-                                       : (mm * q + (double)q * (q + 1));
-      sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
-                    : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
     }
     fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
     ++attempts;
     ok = (p <= 16 && mlo) ? chol_upper_wave(M, p, &cflag, a.rinv) : chol_blocked(M, p, mlo, vw, &cflag, a.rinv);
     if (ok) break;
     if (!shifted) {
+      if (pol == 1) break;   // no shift: the breakdown ends the call
       need_shift = true;
       continue;
     }
+    if (pol != 0) break;     // the fixed shift, or a no-shift first pass, failed
     if (esc >= a.max_escalations) break;
     ++esc;
     sigma = fmax(10.0 * sigma, 2.0 * ufl);

@@ -33,6 +33,7 @@ def test_default_opts_are_the_papers_settings(sq):
     assert o.unit_roundoff == 2.0 ** -53
     assert o.first_pass_shift == 1 and o.min_passes == 3  # CholQR3 start
     assert o.precision == 0 and o.max_escalations == 32 and o.power_steps == 30
+    assert o.shift_policy == 0 and o.append_shift_dim == 0  # Algorithms 1 and 2 as printed
 
 
 def _orth(sq, m, n, lda, ldq, cap, ldr, A=1, Q=1, R=1, opts=None):
@@ -57,6 +58,9 @@ def test_usage_errors_before_any_gpu_work(sq):
     assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=bad) == sq.SQR_EOPT
     bad = sq.sqr_default_opts(max_iter=0)
     assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=bad) == sq.SQR_EOPT
+    for kw in (dict(shift_policy=3), dict(shift_policy=-1), dict(append_shift_dim=3),
+               dict(shift_policy=1, precision=1), dict(shift_policy=2, precision=1)):
+        assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=sq.sqr_default_opts(**kw)) == sq.SQR_EOPT, kw
     assert sq.lib.sqr_append(None, ctypes.c_void_p(0x1000), 1, 1, None, None) == sq.SQR_ENULL
     assert sq.lib.sqr_cols(None) == 0
     sq.lib.sqr_free(None)
@@ -85,3 +89,33 @@ def test_serving_workload_recipe():
     arr = [r.arrival for r in sorted(reqs, key=lambda r: r.rid)]
     assert all(b > a for a, b in zip(arr, arr[1:]))
     assert abs(arr[-1] / len(arr) - 0.01) < 0.002      # mean gap 1 / rate
+
+
+def test_variant_options_match_the_oracle(sq):
+    """The binding's variant table and the oracle's name the same settings."""
+    from oracle import cholqr as O
+    assert set(sq.VARIANTS) == set(O.VARIANTS)
+    for name, kw in sq.VARIANTS.items():
+        assert kw == O.VARIANTS[name], name
+
+
+def test_wrapper_rejects_bad_shapes_before_the_library(sq):
+    """The C ABI sees only pointers and leading dimensions, so the binding
+    checks shapes and devices first (host tensors: nothing reaches a GPU)."""
+    import torch
+    A = torch.zeros(4, 10).t()                     # 10 x 4, column-major
+    with pytest.raises(ValueError):
+        sq.sqr_orth(A, cap=6, Q=torch.zeros(5, 10).t(), R=torch.zeros(6, 6))   # Q too narrow
+    with pytest.raises(ValueError):
+        sq.sqr_orth(A, cap=6, Q=torch.zeros(6, 9).t(), R=torch.zeros(6, 6))    # Q too short
+    with pytest.raises(ValueError):
+        sq.sqr_orth(A, cap=6, Q=torch.zeros(6, 10).t(), R=torch.zeros(6, 5))   # R too small
+    with pytest.raises(ValueError):
+        sq.sqr_orth(A, cap=6, Q=torch.zeros(6, 10, device="meta").t(), R=torch.zeros(6, 6))
+    with pytest.raises(ValueError):
+        sq.sqr_orth(A, cap=3)                                                   # cap < n
+    b = sq.Basis(None, torch.zeros(8, 10).t(), torch.zeros(8, 8), 10, 8)
+    with pytest.raises(ValueError):
+        sq.sqr_append(b, torch.zeros(2, 9).t())                                 # W rows != m
+    with pytest.raises(ValueError):
+        sq.sqr_append(b, torch.zeros(2, 10, device="meta").t())

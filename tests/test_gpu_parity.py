@@ -19,7 +19,7 @@ from oracle import cholqr as O
 
 pytestmark = pytest.mark.gpu
 
-sq = pytest.importorskip("paper_2507_07788_amd")
+import paper_2507_07788_amd as sq  # noqa: E402  (a missing library fails, not skips)
 from gpu_util import dev, host  # noqa: E402
 
 
@@ -532,3 +532,215 @@ def test_append_fills_capacity_528():
     _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e3)
     with pytest.raises(RuntimeError):
         sq.sqr_append(b, dev(A[:, :1]))
+
+
+# --------------------------------------------------------------------------
+# status paths: the escalation cap, non-finite appends, the append entry
+# case, the stopping test at an exact non-zero distance
+# --------------------------------------------------------------------------
+def _dup_hadamard(k=4):
+    """[h1, h1, h2, h3]: an exact Gramian with the zero pivot 256 - 16 * 16."""
+    H = S.hadamard(4 ** k)
+    return np.asfortranarray(np.stack([H[:, 1], H[:, 1], H[:, 2], H[:, 3]], axis=1))
+
+
+@pytest.mark.parametrize("cap", [0, 1, 3])
+def test_orth_breakdown_at_the_escalation_cap(cap):
+    """Algorithm 1 as printed with u = 2^-80 on exactly dependent columns:
+    every shift up to 1e3 sigma0 rounds away against the Gramian's entries,
+    so each factorisation meets the same exact zero pivot and the call ends
+    with SQR_BREAKDOWN after 2 + cap factorisations, as in the oracle."""
+    A = _dup_hadamard()
+    kw = dict(first_pass_shift=0, min_passes=0, unit_roundoff=2.0 ** -80, max_escalations=cap)
+    _, _, io = O.orth(A, **kw)
+    assert io["status"] == O.BREAKDOWN and io["chol_attempts"] == 2 + cap
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == sq.SQR_BREAKDOWN
+    assert info["chol_attempts"] == io["chol_attempts"] and info["passes"] == 0
+    assert info["converged"] == 0
+
+
+@pytest.mark.parametrize("cap", [0, 2])
+def test_append_breakdown_keeps_width(cap):
+    """Two identical new columns orthogonal to the basis: X = [[1, 1], [1, 1]]
+    exactly; with u = 2^-80 and a small cap the append ends with
+    SQR_BREAKDOWN, the width is unchanged, and the basis then takes a
+    regular append."""
+    k, q = 4, 6
+    m = 4 ** k
+    H = S.hadamard(m)
+    A1 = H[:, :q] * 3.0
+    h = H[:, q]
+    W = np.asfortranarray(np.stack([h, h], axis=1))
+    kw = dict(unit_roundoff=2.0 ** -80, max_escalations=cap)
+    _, _, io = O.append(H[:, :q] / 16.0, 3.0 * 16.0 * np.eye(q), W, **kw)
+    assert io["status"] == O.BREAKDOWN
+    b, info = sq.sqr_orth(dev(A1), cap=q + 3, opts=sq.sqr_default_opts(first_pass_shift=0, min_passes=0, **kw))
+    assert info["status"] == 0
+    Q0, R0 = host(b.q()), host(b.r())
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == sq.SQR_BREAKDOWN
+    assert info["chol_attempts"] == io["chol_attempts"] == 2 + cap
+    assert b.n == q
+    assert np.array_equal(host(b.q()), Q0) and np.array_equal(host(b.r()), R0)
+    info = sq.sqr_append(b, dev(H[:, q + 1:q + 2] * 5.0))
+    assert info["status"] == 0 and b.n == q + 1
+    assert np.array_equal(host(b.r())[:q, q], np.zeros(q))
+    assert host(b.r())[q, q] == 5.0 * 16.0
+
+
+def test_append_nonfinite_keeps_width():
+    A1 = S.test_matrix(3000, 12, 1e3, seed=(90,))
+    W = S.test_matrix(3000, 5, 1e2, seed=(91,))
+    W[1234, 2] = np.nan
+    _, _, io = O.append(*O.orth(A1)[:2], W)
+    assert io["status"] == O.ENONFINITE
+    b, info = sq.sqr_orth(dev(A1), cap=20)
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == sq.SQR_ENONFINITE and b.n == 12
+    W[1234, 2] = np.inf
+    assert sq.sqr_append(b, dev(W))["status"] == sq.SQR_ENONFINITE and b.n == 12
+    W[1234, 2] = 0.5
+    assert sq.sqr_append(b, dev(W))["status"] == 0 and b.n == 17
+
+
+@pytest.mark.parametrize("k,q,p", [(4, 12, 5), (5, 40, 16), (5, 20, 37)])
+def test_append_entry_case_bitwise(k, q, p):
+    """W = Q_in C + H_p / 2^k: the initial Schur complement is I exactly while
+    B~ = C.  One pass applies the projection (Prop. 2.1): Q = H_p / 2^k,
+    B = C, R = I bit for bit, on the device as in the oracle."""
+    m = 4 ** k
+    H = S.hadamard(m)
+    Qin = H[:, :q] / 2.0 ** k
+    C = np.random.default_rng(17 + q).integers(-3, 4, size=(q, p)).astype(np.float64)
+    W = Qin @ C + H[:, q:q + p] / 2.0 ** k
+    Qo, Ro, io = O.append(Qin, np.eye(q), W)
+    assert io["passes"] == 1
+    kw = dict(first_pass_shift=0, min_passes=0)
+    b, info = sq.sqr_orth(dev(H[:, :q]), cap=q + p, opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == 0 and info["passes"] == 1 and b.n == q + p
+    Rg = host(b.r())
+    assert np.array_equal(host(b.q())[:, q:], H[:, q:q + p] / 2.0 ** k)
+    assert np.array_equal(Rg[:q, q:], C * 2.0 ** k / 2.0 ** k)
+    assert np.array_equal(Rg[q:, q:], np.eye(p))
+    assert info["orth_fro"] == 0.0
+
+
+@pytest.mark.parametrize("tol,passes", [(3.5, 0), (3.0, 1)])
+def test_stop_test_is_strict_on_the_frobenius_distance(tol, passes):
+    """A = [2 h1, h2] / 8: ||X - I||_F = 3 exactly.  tol 3.5 stops before any
+    pass (Q = A, R = I), tol 3 does not (one exact pass)."""
+    H = S.hadamard(64)
+    A = np.asfortranarray(np.stack([2.0 * H[:, 0], H[:, 1]], axis=1) / 8.0)
+    kw = dict(first_pass_shift=0, min_passes=0, tol=tol)
+    Qo, Ro, io = O.orth(A, **kw)
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+    assert info["status"] == 0 and info["passes"] == io["passes"] == passes
+    assert info["orth_fro"] == io["orth_fro"] == (3.0 if passes == 0 else 0.0)
+    assert np.array_equal(host(b.q()), Qo) and np.array_equal(host(b.r()), Ro)
+
+
+@pytest.mark.parametrize("dim", [0, 1, 2])
+def test_append_first_shift_dimension(dim):
+    """Algorithm 2's first shift with d = q (as printed), p or q + p: the
+    duplicated column pair breaks down unshifted and factors at the first
+    shift, which the device publishes."""
+    k, q = 4, 6
+    H = S.hadamard(4 ** k)
+    W = np.asfortranarray(np.stack([H[:, q], H[:, q]], axis=1) / 16.0)
+    _, _, io = O.append(H[:, :q] / 16.0, np.eye(q), W, append_shift_dim=dim)
+    b, info = sq.sqr_orth(dev(H[:, :q] / 16.0), cap=q + 2,
+                          opts=sq.sqr_default_opts(first_pass_shift=0, min_passes=0,
+                                                   append_shift_dim=dim))
+    info = sq.sqr_append(b, dev(W))
+    want = io["shift_tries"][0]
+    assert info["chol_attempts"] >= 2 and info["sigma"][0] > 0.0
+    assert abs(info["sigma"][0] - want) <= 1e-12 * want
+
+
+# --------------------------------------------------------------------------
+# the Cholesky QR variants (Sec. 3.1) and Fig. 1's pattern on the device
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", sorted(sq.VARIANTS))
+def test_variants_fig1_pattern_on_the_device(variant):
+    """Each variant on 300 x 10 inputs with kappa = 10^0 .. 10^20 through the
+    library, against the oracle's variant: the same status wherever the
+    oracle is away from its own transition (it reaches the same status at the
+    neighbouring decades too), LOO and RRR of every successful call as in
+    the oracle, and the robustness pattern of Fig. 1."""
+    kw = sq.VARIANTS[variant]
+    st, ost, loo = {}, {}, {}
+    for e in range(0, 21):
+        A = S.test_matrix(300, 10, 10.0 ** e, seed=(6,))
+        Qo, Ro, io = O.orth(A, **kw)
+        b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(**kw))
+        st[e], ost[e] = info["status"], io["status"]
+        Qg, Rg = host(b.q()), host(b.r())
+        loo[e] = O.loo(Qg)
+        if info["status"] == 0:
+            assert abs(info["passes"] - io["passes"]) <= 1, e
+            assert loo[e] <= max(1e-13, 1e2 * O.loo(Qo)), e
+            assert O.rrr(A, Qg, Rg) <= 1e-13, e
+        sq.sqr_free(b)
+    for e in range(0, 21):
+        stable = all(ost.get(f, ost[e]) == ost[e] for f in (e - 1, e + 1))
+        if stable:
+            assert st[e] == ost[e], (variant, e, st, ost)
+    if variant in ("rsCholQR", "isCholQR", "CholQR3"):
+        assert all(v == 0 for v in st.values()) and max(loo.values()) <= 1e-13
+    if variant in ("CholQR", "CholQR2"):
+        assert all(st[e] == sq.SQR_BREAKDOWN for e in range(10, 21))
+
+
+# --------------------------------------------------------------------------
+# one handle, calls on alternating streams
+# --------------------------------------------------------------------------
+def test_alternating_streams_match_one_stream():
+    """Calls of one handle on two streams are ordered (the later call waits
+    for the earlier call's stream): orth, then appends alternating between
+    the streams, equals the single-stream run bit for bit."""
+    A0, Ws, _ = S.growth_blocks(60_000, 10, 10, 8, 1e2, 1e10)
+    A0d = dev(A0)
+    Wd = [dev(W) for W in Ws]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    out = []
+    for streams in ((s1, s1), (s1, s2)):
+        b, info = sq.sqr_orth(A0d, cap=90, stream=streams[0])
+        assert info["status"] == 0
+        for i, W in enumerate(Wd):
+            info = sq.sqr_append(b, W, stream=streams[(i + 1) % 2])
+            assert info["status"] == 0
+        torch.cuda.synchronize()
+        out.append((b.q().clone(), b.r().clone()))
+        sq.sqr_free(b)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert O.loo(host(out[1][0])) <= 1e-12
+
+
+@pytest.mark.slow
+def test_append_growth_full_1e6_elementwise():
+    """Basis growth at m = 1e6 (10 -> 200 columns) with block kappa up to 1e6,
+    where the factors are unique to working accuracy: R (with B) element by
+    element against the oracle within 1e-10 kappa ||R||, and sampled rows of
+    Q likewise."""
+    m, nb, p = 1_000_000, 19, 10
+    A0, Ws, kap = S.growth_blocks(m, 10, p, nb, 1e2, 1e6, seed=3)
+    Qo, Ro, io = O.orth(A0)
+    for W in Ws:
+        Qo, Ro, io = O.append(Qo, Ro, W)
+        assert io["status"] == 0
+    b, info = sq.sqr_orth(dev(A0), cap=10 + p * nb)
+    for W in Ws:
+        assert sq.sqr_append(b, dev(W))["status"] == 0
+    Rg = host(b.r())
+    tol = 1e-10 * 1e6 * np.linalg.norm(Ro)
+    assert np.max(np.abs(Rg - Ro)) <= tol
+    assert np.linalg.norm(Rg - Ro) <= 1e-10 * 1e6 * np.linalg.norm(Ro)
+    rows = np.random.default_rng(2).choice(m, 3000, replace=False)
+    Qg = b.q()[torch.as_tensor(rows, device=b.Q.device)].cpu().numpy()
+    assert np.max(np.abs(Qg - Qo[rows])) <= 1e-10 * 1e6
+    A = np.concatenate([A0] + Ws, axis=1)
+    assert O.rrr(A, host(b.q()), Rg) <= 1e-13
