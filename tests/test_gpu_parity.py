@@ -691,7 +691,12 @@ def test_variants_fig1_pattern_on_the_device(variant):
     if variant in ("rsCholQR", "isCholQR", "CholQR3"):
         assert all(v == 0 for v in st.values()) and max(loo.values()) <= 1e-13
     if variant in ("CholQR", "CholQR2"):
-        assert all(st[e] == sq.SQR_BREAKDOWN for e in range(10, 21))
+        # kappa = 1e10 is the oracle's own transition decade: the two
+        # smallest eigenvalues of the Gramian (1e-20, 1.7e-18) lie below its
+        # rounding noise (~u), so whether a pivot turns non-positive depends
+        # on the summation order (a call that gets through is graded by the
+        # LOO and RRR checks above).
+        assert all(st[e] == sq.SQR_BREAKDOWN for e in range(11, 21)), st
 
 
 # --------------------------------------------------------------------------
