@@ -727,25 +727,32 @@ def test_alternating_streams_match_one_stream():
 
 @pytest.mark.slow
 def test_append_growth_full_1e6_elementwise():
-    """Basis growth at m = 1e6 (10 -> 200 columns) with block kappa up to 1e6,
-    where the factors are unique to working accuracy: R (with B) element by
-    element against the oracle within 1e-10 kappa ||R||, and sampled rows of
-    Q likewise."""
+    """Basis growth at m = 1e6 (10 -> 200 columns) with block kappa up to 1e6.
+    The accumulated matrix [A0 W_1 .. W_19] is numerically singular (its
+    condition number passes 1e15 after a few blocks: every block is coupled to
+    the span of the earlier ones), so the global factors are not unique; the
+    block of each append is, given the basis it is appended to (Prop. 2.1).
+    So every append of the device run is compared with the oracle's append on
+    the device's own basis Q_in, R_in: B, the new diagonal block of R and the
+    new columns of Q element by element within 1e-10 kappa_k times their norm.
+    The whole basis is graded on LOO and RRR."""
     m, nb, p = 1_000_000, 19, 10
     A0, Ws, kap = S.growth_blocks(m, 10, p, nb, 1e2, 1e6, seed=3)
-    Qo, Ro, io = O.orth(A0)
-    for W in Ws:
-        Qo, Ro, io = O.append(Qo, Ro, W)
-        assert io["status"] == 0
     b, info = sq.sqr_orth(dev(A0), cap=10 + p * nb)
+    Qo0, Ro0, _ = O.orth(A0)
+    _check_factors(A0, host(b.q()), host(b.r()), Qo0, Ro0, 1e2)
     for W in Ws:
         assert sq.sqr_append(b, dev(W))["status"] == 0
-    Rg = host(b.r())
-    tol = 1e-10 * 1e6 * np.linalg.norm(Ro)
-    assert np.max(np.abs(Rg - Ro)) <= tol
-    assert np.linalg.norm(Rg - Ro) <= 1e-10 * 1e6 * np.linalg.norm(Ro)
-    rows = np.random.default_rng(2).choice(m, 3000, replace=False)
-    Qg = b.q()[torch.as_tensor(rows, device=b.Q.device)].cpu().numpy()
-    assert np.max(np.abs(Qg - Qo[rows])) <= 1e-10 * 1e6
+    Qg, Rg = host(b.q()), host(b.r())
+    for k, W in enumerate(Ws):
+        q = 10 + p * k
+        Qn, Rn, io = O.append(Qg[:, :q], Rg[:q, :q], W)
+        assert io["status"] == 0, k
+        tol = 1e-10 * kap[k]
+        nrm = np.linalg.norm(Rn[:, q:])
+        assert np.max(np.abs(Rg[:q, q:q + p] - Rn[:q, q:])) <= tol * nrm, k        # B
+        assert np.max(np.abs(Rg[q:q + p, q:q + p] - Rn[q:, q:])) <= tol * nrm, k   # R_kk
+        assert np.max(np.abs(Qg[:, q:q + p] - Qn[:, q:])) <= tol, k                # Q_k
+    assert O.loo(Qg) <= 1e-12
     A = np.concatenate([A0] + Ws, axis=1)
-    assert O.rrr(A, host(b.q()), Rg) <= 1e-13
+    assert O.rrr(A, Qg, Rg) <= 1e-13
