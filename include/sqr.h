@@ -35,6 +35,12 @@ extern "C" {
 #define SQR_EDIM          (-2) /* inconsistent sizes or leading dimensions     */
 #define SQR_EHIP          (-3) /* HIP runtime error or device out of memory    */
 #define SQR_EOPT          (-4) /* an option value outside its documented range */
+#define SQR_ELIMIT        (-5) /* sqr_orth_noalloc: the call needs more than its
+                                  static scratch holds                         */
+
+/* Limits of sqr_orth_noalloc: columns, and bytes of its per-GPU scratch. */
+#define SQR_NOALLOC_MAX_COLS       128
+#define SQR_NOALLOC_SCRATCH_BYTES  (24ll << 20)
 
 /* Options.  Defaults (sqr_default_opts) are the paper's experimental settings
  * (Sec. 3.1: tolerance 1e-13 on ||I - Q^T Q||_F, at most 10 iterations). */
@@ -130,6 +136,38 @@ void sqr_default_opts(sqr_opts* o);
 int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
              const double* A, int64_t lda, double* Q, int64_t ldq, int64_t cap,
              double* R, int64_t ldr, void* stream, sqr_info* info);
+
+/*
+ * sqr_orth_noalloc -- for callers that cannot allocate device memory (code
+ * that a HIP graph captures, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation of sqr_orth (same kernels, same options; with
+ * the same slot count the result is bit for bit that of sqr_orth) without a
+ * handle, without pinned host memory and without any hipMalloc/hipFree.
+ * Its workspace (partial Gramians, small matrices, control block) is one
+ * static device array of SQR_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * first call on that GPU until the process ends.
+ *
+ *   A, lda   m x n input (n <= SQR_NOALLOC_MAX_COLS), read only.
+ *   Q, ldq   m x n output; R, ldr: n x n output (ldr >= n), as in sqr_orth.
+ *   stream   hipStream_t; every pass up to max_iter is enqueued (passes
+ *            after the device's decision exit at once).
+ *   info     NULL: nothing waits, the call only enqueues work; non-NULL:
+ *            the outcome is copied from the device and the stream is
+ *            synchronised (not allowed during stream capture).
+ *
+ * All calls on one GPU share its scratch array and the array keeps the last
+ * call's contents (every call starts from its own cleared state): calls that
+ * overlap on one GPU -- on different streams, or from different host threads
+ * without ordering -- race and give wrong results.  Order them on one stream.
+ * The first call on a device looks the array up (hipGetSymbolAddress); make
+ * it outside any stream capture.
+ * Errors: SQR_ENULL, SQR_EDIM (as sqr_orth with cap = n), SQR_ELIMIT
+ * (n > SQR_NOALLOC_MAX_COLS), SQR_EOPT, SQR_EHIP; all before any work is
+ * enqueued, except SQR_EHIP from a failed launch.
+ */
+int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A, int64_t lda,
+                     double* Q, int64_t ldq, double* R, int64_t ldr, void* stream,
+                     sqr_info* info);
 
 /*
  * sqr_append -- Algorithm 2: extend the basis Q[:, 0:n] of handle b by the p

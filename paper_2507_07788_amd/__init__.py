@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsqr.so")
 
 SQR_OK, SQR_NOT_CONVERGED, SQR_BREAKDOWN, SQR_ENONFINITE = 0, 1, 2, 3
-SQR_ENULL, SQR_EDIM, SQR_EHIP, SQR_EOPT = -1, -2, -3, -4
+SQR_ENULL, SQR_EDIM, SQR_EHIP, SQR_EOPT, SQR_ELIMIT = -1, -2, -3, -4, -5
 
 
 class SqrOpts(ctypes.Structure):
@@ -67,6 +67,9 @@ def _load():
     lib.sqr_orth.argtypes = [ctypes.POINTER(P), ctypes.POINTER(SqrOpts), I64, I64, P, I64,
                              P, I64, I64, P, I64, P, ctypes.POINTER(SqrInfo)]
     lib.sqr_orth.restype = I32
+    lib.sqr_orth_noalloc.argtypes = [ctypes.POINTER(SqrOpts), I64, I64, P, I64, P, I64,
+                                     P, I64, P, ctypes.POINTER(SqrInfo)]
+    lib.sqr_orth_noalloc.restype = I32
     lib.sqr_append.argtypes = [P, P, I64, I64, P, ctypes.POINTER(SqrInfo)]
     lib.sqr_append.restype = I32
     lib.sqr_last_info.argtypes = [P, ctypes.POINTER(SqrInfo)]
@@ -174,6 +177,27 @@ def sqr_orth(A: torch.Tensor, cap: int | None = None, opts: SqrOpts | None = Non
     if rc < 0:
         raise RuntimeError(f"sqr_orth failed with code {rc}")
     return Basis(h, Q, R, m, cap), (info.as_dict() if sync else None)
+
+
+def sqr_orth_noalloc(A: torch.Tensor, Q: torch.Tensor, R: torch.Tensor,
+                     opts: SqrOpts | None = None, stream=None, sync: bool = True):
+    """Q R = A into the caller's Q (m x n) and R (n x n) with the library's
+    static per-GPU scratch (sqr_orth_noalloc: no device allocation, no
+    handle).  Returns the info dict (sync) or None; raises ValueError on
+    inconsistent shapes or devices and RuntimeError on other usage errors."""
+    if A.dim() != 2:
+        raise ValueError("A must be a matrix")
+    m, n = A.shape
+    _check_matrix("Q", Q, m, n, A.device)
+    _check_matrix("R", R, n, n, A.device)
+    info = SqrInfo()
+    rc = lib.sqr_orth_noalloc(ctypes.byref(opts) if opts is not None else None,
+                              m, n, A.data_ptr(), _ld(A), Q.data_ptr(), _ld(Q),
+                              R.data_ptr(), _ld(R), _stream(stream),
+                              ctypes.byref(info) if sync else None)
+    if rc < 0:
+        raise RuntimeError(f"sqr_orth_noalloc failed with code {rc}")
+    return info.as_dict() if sync else None
 
 
 def sqr_append(b: Basis, W: torch.Tensor, stream=None) -> dict:

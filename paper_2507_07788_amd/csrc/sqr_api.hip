@@ -73,7 +73,7 @@ void prof_finalize(int64_t id, int passes) {
 // Event pair around the launches of one streaming step (when recording).
 ProfRec prof_begin(int kind, double bytes, int64_t call, int phase, hipStream_t s) {
   ProfRec rec{};
-  if (!g_prof_on) return rec;
+  if (!g_prof_on || call < 0) return rec;   // call < 0: a call that records nothing
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     rec.e0 = take_event();
@@ -153,6 +153,7 @@ struct sqr_basis {
   Ctrl* ctrl = nullptr;
   Ctrl last{};                       // outcome of the last call (kept while parked)
   bool parked = false;               // workspace returned to the pool
+  bool noprof = false;               // never recorded by the profiling hooks
   Ctrl* ctrl_host = nullptr;         // pinned, written by small_step
   Ctrl* ctrl_host_dev = nullptr;     // its device address
   double *part = nullptr, *stage = nullptr;
@@ -322,24 +323,59 @@ int64_t worst_bneg_len(int64_t cap) {
   return w;
 }
 
-int alloc_workspace(sqr_basis* b) {
-  const int64_t cap = b->cap;
-  const int64_t tl = worst_total_len(cap);
-  const int64_t tiles = (b->m + 15) / 16;
+// Sizes (doubles) of the workspace regions of a handle.
+struct WsSizes { int64_t tl, arena, bneg, rinv; };
+
+// Every call a handle of capacity cap can make (q + p <= cap).
+WsSizes handle_sizes(int64_t cap) {
+  WsSizes z;
+  z.tl = worst_total_len(cap);
+  z.arena = 0;
+  for (int64_t p = 1; p <= cap; ++p) z.arena = std::max<int64_t>(z.arena, small_arena((int)(cap - p), (int)p));
+  z.bneg = worst_bneg_len(cap);
+  z.rinv = nblocks(cap) * 256;
+  return z;
+}
+
+// One orthogonalisation of n columns (no later appends).
+WsSizes orth_sizes(int64_t n) {
+  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256};
+}
+
+// Partial-Gram slots for m rows: one per resident workgroup at most, within
+// the slot budget.
+int default_slots(int64_t m, int64_t tl) {
+  const int64_t tiles = (m + 15) / 16;
   int64_t slots = std::min<int64_t>(kMaxSlots, (tiles + kWaves - 1) / kWaves);
   slots = std::min<int64_t>(slots, std::max<int64_t>(16, kPartBudget / (8 * tl)));
-  b->slots = (int)std::max<int64_t>(1, slots);
-  const int64_t sq = cap * cap;
-  int64_t arena = 0;
-  for (int64_t p = 1; p <= cap; ++p) arena = std::max<int64_t>(arena, small_arena((int)(cap - p), (int)p));
+  return (int)std::max<int64_t>(1, slots);
+}
+
+// Lay the regions out from `base` (NULL: only measure); returns the doubles
+// used.  Sets the handle's region pointers when base is not NULL.
+size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) {
   size_t doubles = 0;
   auto take = [&](int64_t n) { size_t off = doubles; doubles += (size_t)round4(n) + 32; return off; };
-  const size_t o_part = take((int64_t)b->slots * tl);
-  const size_t o_stage = take(tl);        // reduced Gramian blocks of a pass
-  const size_t o_X = take(arena);
-  const size_t o_bneg = take(worst_bneg_len(cap));
-  const size_t o_rinv = take(nblocks(cap) * 256);
+  const size_t o_part = take((int64_t)slots * z.tl);
+  const size_t o_stage = take(z.tl);        // reduced Gramian blocks of a pass
+  const size_t o_X = take(z.arena);
+  const size_t o_bneg = take(z.bneg);
+  const size_t o_rinv = take(z.rinv);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
+  if (base) {
+    b->slots = slots;
+    b->part = base + o_part; b->stage = base + o_stage;
+    b->X = base + o_X;
+    b->bneg = base + o_bneg; b->rinv = base + o_rinv;
+    b->ctrl = (Ctrl*)(base + o_ctrl);
+  }
+  return doubles;
+}
+
+int alloc_workspace(sqr_basis* b) {
+  const WsSizes z = handle_sizes(b->cap);
+  const int slots = default_slots(b->m, z.tl);
+  const size_t doubles = carve_workspace(b, nullptr, z, slots);
   {
     CachedWs e;
     if (pool_take(b->device, doubles * 8, &e)) {
@@ -351,11 +387,7 @@ int alloc_workspace(sqr_basis* b) {
     if (hipMalloc(&b->ws, doubles * 8) != hipSuccess) { b->ws = nullptr; return SQR_EHIP; }
     b->ws_bytes = doubles * 8;
   }
-  double* base = (double*)b->ws;
-  b->part = base + o_part; b->stage = base + o_stage;
-  b->X = base + o_X;
-  b->bneg = base + o_bneg; b->rinv = base + o_rinv;
-  b->ctrl = (Ctrl*)(base + o_ctrl);
+  carve_workspace(b, (double*)b->ws, z, slots);
   if (!b->ctrl_host &&
       hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -401,7 +433,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     // launches between one pair of profiling events (the mixed form's two
     // Gramian variants count as one launch: one of them exits at once)
     auto timed = [&](int kind, double bytes, auto&& enqueue) {
-      const ProfRec rec = prof_begin(kind, bytes, b->call_id, phase, s);
+      const ProfRec rec = prof_begin(kind, bytes, b->noprof ? -1 : b->call_id, phase, s);
       if (!enqueue()) return false;
       prof_end(rec, s);
       return true;
@@ -452,7 +484,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.copy_if_done = (phase == 1);
     void* args[] = {&w};
     const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
-                                   b->call_id, phase, s);
+                                   b->noprof ? -1 : b->call_id, phase, s);
     if (hipLaunchKernel((const void*)kNarrow[apply ? 1 : 0], dim3((unsigned)nwg), dim3(kThreads), args, 0, s) !=
         hipSuccess)
       return SQR_EHIP;
@@ -479,7 +511,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.copy_if_done = (phase == 1);
     void* args[] = {&w};
     const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
-                                   b->call_id, phase, s);
+                                   b->noprof ? -1 : b->call_id, phase, s);
     for (int g32 = mixed ? 1 : 0; g32 >= 0; --g32) {
       // phase 0 of the mixed form is an FP32 Gramian; later phases follow the
       // device (ctrl->gram32); FP64 calls launch the FP64 variant only
@@ -526,7 +558,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     const Variant* v = pick_variant((ks + 15) / 16);
     void* args[] = {&a};
     const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)(ks + (apply ? 2 : 1) * a.pb),
-                                   b->call_id, phase, s);
+                                   b->noprof ? -1 : b->call_id, phase, s);
     if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
                         dim3(kThreads), args, block_lds_bytes(*v, apply), s) != hipSuccess)
       return SQR_EHIP;
@@ -637,6 +669,32 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   return SQR_OK;
 }
 
+// ---- the allocation-free orthogonalisation (sqr_orth_noalloc): its
+// workspace is one file-scope device array per GPU, `scratch`.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in
+// symbol, not a device address): the device address is looked up once per
+// device with hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr int64_t kScratchDoubles = SQR_NOALLOC_SCRATCH_BYTES / 8;
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (NULL on failure).
+double* scratch_on_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 bool opts_ok(const sqr_opts& o) {
   return (o.precision == 0 || o.precision == 1) && o.max_iter >= 1 && o.max_iter <= 64 && o.min_passes >= 0 &&
          o.tol > 0.0 && o.unit_roundoff > 0.0 && o.max_escalations >= 0 &&
@@ -692,6 +750,52 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
     return info->status;
   }
   return SQR_OK;
+}
+
+int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A, int64_t lda,
+                     double* Q, int64_t ldq, double* R, int64_t ldr, void* stream, sqr_info* info) {
+  if (!A || !Q || !R) return SQR_ENULL;
+  if (m < 1 || n < 1 || n > m || lda < m || ldq < m || ldr < n) return SQR_EDIM;
+  if (lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  if (n > SQR_NOALLOC_MAX_COLS) return SQR_ELIMIT;
+  sqr_opts o;
+  sqr_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_ok(o)) return SQR_EOPT;
+  set_kernel_attributes();
+  // A handle on the host stack whose regions lie in this device's scratch
+  // array; no pinned mirror (the outcome is copied from the device), no
+  // measurement records.
+  sqr_basis b;
+  b.m = m; b.n = n; b.cap = n; b.Q = Q; b.ldq = ldq; b.R = R; b.ldr = ldr;
+  b.opts = o;
+  b.noprof = true;
+  if (hipGetDevice(&b.device) != hipSuccess) return SQR_EHIP;
+  double* base = scratch_on_device(b.device);
+  if (!base) return SQR_EHIP;
+  const WsSizes z = orth_sizes(n);
+  // as many slots as sqr_orth would take, as far as the array holds them
+  // (then the reduction order, and so the result, is the same)
+  int slots = default_slots(m, z.tl);
+  const size_t fixed = carve_workspace(&b, nullptr, z, 0);
+  const int64_t fit = ((int64_t)kScratchDoubles - (int64_t)fixed - 64) / (z.tl + 1);
+  if (fit < 1) return SQR_ELIMIT;
+  slots = (int)std::min<int64_t>(slots, fit);
+  if ((int64_t)carve_workspace(&b, nullptr, z, slots) > kScratchDoubles) return SQR_ELIMIT;
+  carve_workspace(&b, base, z, slots);
+  Call c{0, 0, n, A, lda, Q, ldq};
+  hipStream_t s = (hipStream_t)stream;
+  // every pass up to max_iter is enqueued; those after the device's decision
+  // exit at once
+  int rc = run_call(&b, c, s, false, 0);
+  if (rc) return rc;
+  if (!info) return SQR_OK;
+  Ctrl st;
+  if (hipMemcpyAsync(&st, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SQR_EHIP;
+  fill_info(&st, info);
+  return info->status;
 }
 
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stream,

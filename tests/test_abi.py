@@ -119,3 +119,25 @@ def test_wrapper_rejects_bad_shapes_before_the_library(sq):
         sq.sqr_append(b, torch.zeros(2, 9).t())                                 # W rows != m
     with pytest.raises(ValueError):
         sq.sqr_append(b, torch.zeros(2, 10, device="meta").t())
+
+
+def _noalloc(sq, m, n, lda, ldq, ldr, A=1, Q=1, R=1, opts=None):
+    P = lambda v: ctypes.c_void_p(0x1000 if v else 0)  # never dereferenced
+    return sq.lib.sqr_orth_noalloc(ctypes.byref(opts) if opts else None, m, n, P(A), lda,
+                                   P(Q), ldq, P(R), ldr, None, None)
+
+
+def test_noalloc_usage_errors_and_limit_before_any_gpu_work(sq):
+    """sqr_orth_noalloc rejects bad arguments and widths beyond its static
+    scratch (SQR_NOALLOC_MAX_COLS) before any HIP call."""
+    hdr = open(os.path.join(ROOT, "include", "sqr.h")).read()
+    maxc = int(re.search(r"#define SQR_NOALLOC_MAX_COLS\s+(\d+)", hdr).group(1))
+    assert maxc == 128
+    assert _noalloc(sq, 100, 10, 100, 100, 10, A=0) == sq.SQR_ENULL
+    assert _noalloc(sq, 100, 10, 100, 100, 10, R=0) == sq.SQR_ENULL
+    assert _noalloc(sq, 10, 11, 10, 10, 11) == sq.SQR_EDIM        # n > m
+    assert _noalloc(sq, 100, 10, 99, 100, 10) == sq.SQR_EDIM      # lda < m
+    assert _noalloc(sq, 100, 10, 100, 100, 9) == sq.SQR_EDIM      # ldr < n
+    assert _noalloc(sq, 10000, maxc + 1, 10000, 10000, maxc + 1) == sq.SQR_ELIMIT
+    bad = sq.sqr_default_opts(max_iter=0)
+    assert _noalloc(sq, 100, 10, 100, 100, 10, opts=bad) == sq.SQR_EOPT
