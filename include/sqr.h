@@ -129,7 +129,7 @@ void sqr_default_opts(sqr_opts* o);
  * so the calls of one handle are always ordered.  A handle must not be used
  * by two host threads at once.
  * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
- * cap < n, ldr < cap, cap > 528, lda or ldq > 2^27), SQR_EOPT (also for
+ * cap < n, ldr < cap, cap > 528, lda or ldq > 2^25 - 1), SQR_EOPT (also for
  * precision 1 with n > 256), SQR_EHIP; all
  * before any work is enqueued, except SQR_EHIP from a failed launch.
  */
@@ -179,7 +179,7 @@ int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A
  * may be NULL.  At least one pass runs, so the projection of Prop. 2.1 is
  * applied even when the initial Schur complement already passes the
  * stopping test (W = Q_in C + H, H orthonormal and orthogonal to Q_in).
- * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^27, n + p > cap,
+ * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^25 - 1, n + p > cap,
  * n + p > m).
  */
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,

@@ -34,9 +34,9 @@ using namespace sqr;
 namespace {
 
 constexpr int kMaxSlots = 1024;
-// Leading dimensions up to this keep every per-lane buffer offset,
-// (3 ld + m) * 8 bytes, below 4 GiB.
-constexpr int64_t kMaxLd = (int64_t)1 << 27;
+// Leading dimensions below 2^25 keep every per-lane buffer offset inside a
+// 16-column tile, (15 ld + m) * 8 bytes, below 4 GiB.
+constexpr int64_t kMaxLd = ((int64_t)1 << 25) - 1;
 constexpr size_t kPartBudget = 256ull << 20;   // bytes of partial slots per handle
 // small_step arena in LDS up to this (its static LDS, about 25 KB, comes on top)
 constexpr size_t kSmallLdsBytes = 128 * 1024;
@@ -125,14 +125,16 @@ void pool_put(const CachedWs& e) {
 }
 
 int64_t round4(int64_t v) { return (v + 3) & ~int64_t(3); }
+// The basis segment of S is padded to whole 16-column tiles.
+int64_t round16(int64_t v) { return (v + 15) & ~int64_t(15); }
 int64_t nblocks(int64_t p) { return (p + 15) / 16; }
 // Doubles of the reduced partial Gramians of a call with basis q and block p.
 int64_t total_len(int64_t q, int64_t p) {
   const int64_t P = nblocks(p);
-  return 16 * (P * (round4(q) + 16) + 8 * P * (P - 1));
+  return 16 * (P * (round16(q) + 16) + 8 * P * (P - 1));
 }
-int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (round4(q) + 16) + 8 * J * (J - 1)); }
-int64_t bneg_off(int64_t q, int64_t J) { return 16 * (J * round4(q) + 8 * J * (J - 1)); }
+int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (round16(q) + 16) + 8 * J * (J - 1)); }
+int64_t bneg_off(int64_t q, int64_t J) { return 16 * (J * round16(q) + 8 * J * (J - 1)); }
 int64_t bneg_len(int64_t q, int64_t p) { return bneg_off(q, nblocks(p)); }
 
 }  // namespace
@@ -528,7 +530,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   // together): resident workgroups of the most demanding block's variant,
   // capped by the slot capacity and by the row tiles available.
   for (int64_t J = 0; J < P; ++J) {
-    const int ks = (int)round4(c.q) + (int)(16 * J);
+    const int ks = (int)round16(c.q) + (int)(16 * J);
     const Variant* v = pick_variant((ks + 15) / 16);
     if (!v) return SQR_EDIM;
     const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
@@ -554,10 +556,12 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     a.done = phase > 0 ? &b->ctrl->done : nullptr;  // phase 0 starts the call
     a.passes = &b->ctrl->passes;
     a.copy_if_done = (phase == 1);
-    const int ks = (int)round4(a.n1) + a.n2;   // columns of S with the padding
+    const int ks = (int)round16(a.n1) + a.n2;   // columns of S with the padding
     const Variant* v = pick_variant((ks + 15) / 16);
     void* args[] = {&a};
-    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)(ks + (apply ? 2 : 1) * a.pb),
+    // algorithmic bytes: the real columns of S (no padding), the block read,
+    // and (apply) the block written
+    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)(a.n1 + a.n2 + (apply ? 2 : 1) * a.pb),
                                    b->noprof ? -1 : b->call_id, phase, s);
     if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
                         dim3(kThreads), args, block_lds_bytes(*v, apply), s) != hipSuccess)

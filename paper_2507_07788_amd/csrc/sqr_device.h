@@ -36,7 +36,7 @@ struct BlockPassArgs {
   const double* s2;   int64_t ld2;  int32_t n2;   // same-pass prefix of S
   int32_t pb;                         // real columns of the block (1..16)
   int64_t m;                          // rows
-  const double* bneg;                 // (n1+n2 rounded up to 4) x 16, row-major: -B~_J
+  const double* bneg;                 // (n1 rounded up to 16, + n2) x 16, row-major: C_J
   const double* rinv;                 // 16 x 16 row-major inverse of the diagonal block
   double* part; int64_t part_stride; int64_t part_off;  // slot b at part + b*stride + off
   const int32_t* done;                // NULL in the initial Gram pass of a call

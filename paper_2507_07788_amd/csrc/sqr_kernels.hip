@@ -74,9 +74,10 @@ constexpr int kWaves = 4;             // waves per workgroup of block_pass
 constexpr int kThreads = 64 * kWaves;
 constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
 
-// S is the concatenation [s1 (n1 columns) | zero padding up to q4 = n1
-// rounded up to 4 | s2 (n2 columns, a multiple of 16)], so every k-slice of
-// four columns lies in a single segment.  ks = q4 + n2 columns in all.
+// S is the concatenation [s1 (n1 columns) | zero padding up to q16 = n1
+// rounded up to 16 | s2 (n2 columns, a multiple of 16)], so every 16-column
+// tile of S lies in a single segment and is read through one buffer
+// descriptor.  ks = q16 + n2 columns in all.
 //
 // Work split: the four waves of a workgroup form 4/WPT groups of WPT waves;
 // each group processes its own 16-row tile per step, so a workgroup keeps
@@ -89,8 +90,12 @@ constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
 // order at the end.
 constexpr int kTPart = 256;    // doubles per 16x16 tile in LDS
 
+// Waves per SIMD the register allocation must leave room for: three for the
+// variants up to 12 S tiles (their LDS allows three workgroups per CU), one
+// for the wider ones.
 template <int NTW, int WPT, bool APPLY>
-__global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
+void block_pass(BlockPassArgs a) {
   // LDS: double-buffered partial T tiles (2 x 4 x 256 doubles), then one
   // 16x17 transposition tile per wave; the final cross-group reduction
   // reuses the area.
@@ -124,8 +129,8 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
     return;
   }
 
-  const int q4 = (a.n1 + 3) & ~3;      // basis segment padded to whole k-slices
-  const int ks = q4 + a.n2;            // columns of S (a multiple of 4)
+  const int q16 = (a.n1 + 15) & ~15;   // basis segment padded to whole tiles
+  const int ks = q16 + a.n2;            // columns of S (a multiple of 16)
   const int nk = ks >> 2;              // k-slices of four S columns
   const int ns = (ks + 15) >> 4;       // 16-column tiles of S
   double* tpart = lds;                                   // [2][4][256]
@@ -149,84 +154,74 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
   for (int j = 0; j < NTW; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   d4 accg = d4{0.0, 0.0, 0.0, 0.0};
 
-  // Loads of one row tile: my S slices and the block input.
-  auto load_tile = [&](int64_t tl, double (&sreg)[NTW][4], d4& w) {
-    const int64_t row = tl * 16 + x;
-    const bool row_ok = row < a.m;
-    const int64_t rowc = row_ok ? row : a.m - 1;
-    {
-      // One buffer descriptor per slice: base at the slice's first column,
-      // range = bytes up to the end of the segment's last column, so columns
-      // past a segment (padding, slices past the end of S) read zero in
-      // hardware.  A lane adds only its own offset (g ld + row) * 8.
-      const uint32_t o1 = (uint32_t)(((int64_t)g * a.ld1 + rowc) * 8);
-      const uint32_t o2 = (uint32_t)(((int64_t)g * a.ld2 + rowc) * 8);
+  // Step k of a group handles row tile t0 + k G + grp.  The member that owns
+  // step k (k mod WPT) adds W_J D_J to the apply, stores Y and accumulates
+  // Y^T Y, so this extra work rotates over the members (and their SIMDs).
+  // In the apply only the owner needs the block input; in the Gram-only pass
+  // every member does (Y = W).
+  const int nsteps = (int)((t1 - t0 + G - 1) / G);   // the same for every wave
+  // Loads of one step: my S slices and (if needed) the block input.  One
+  // buffer descriptor per 16-column tile: base at the tile's first column,
+  // range = bytes up to the end of its segment's last column, so columns past
+  // a segment (padding, tiles past the end of S) read zero in hardware.  Lane
+  // (x, g) of slice jj adds ((4 jj + g) ld + row) * 8, below 4 GiB for the
+  // leading dimensions the library accepts.  A tile past the range is
+  // clamped to a valid one and its rows are masked when it is used (keep),
+  // not here, so the loads stay in flight until then.
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win, ((int64_t)(a.pb - 1) * a.ldw + a.m) * 8);
+  auto load_step = [&](int k, double (&sreg)[NTW][4], d4& w, uint64_t& keep) {
+    const int64_t tile = t0 + (int64_t)k * G + grp;
+    const int64_t row = min(tile, t1 - 1) * 16 + x;
+    keep = (tile < t1 && row < a.m) ? ~0ull : 0ull;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
-      for (int j = 0; j < NTW; ++j)
+    for (int j = 0; j < NTW; ++j) {
+      const int I = mem + WPT * j;
+      const bool first = (16 * I < q16) || a.n2 == 0;
+      const int cs = first ? 16 * I : 16 * I - q16;
+      const int hi = first ? hi1 : hi2;
+      const int64_t ld = first ? a.ld1 : a.ld2;
+      const double* base = (first ? a.s1 : a.s2) + (int64_t)cs * ld;
+      const int64_t nrec = (hi >= cs) ? (((int64_t)(hi - cs) * ld + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, nrec);
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int s = 4 * (mem + WPT * j) + jj;
-          const bool first = (4 * s < q4) || a.n2 == 0;
-          const int cs = first ? 4 * s : 4 * s - q4;
-          const int hi = first ? hi1 : hi2;
-          const int64_t ld = first ? a.ld1 : a.ld2;
-          const double* base = (first ? a.s1 : a.s2) + (int64_t)cs * ld;
-          const int64_t nrec = (hi >= cs) ? (((int64_t)(hi - cs) * ld + a.m) * 8) : 0;
-          const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, nrec);
-          sreg[j][jj] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-              rs, (int)(first ? o1 : o2), 0, 0));
-        }
+      for (int jj = 0; jj < 4; ++jj) {
+        const uint32_t o = (uint32_t)(((int64_t)(4 * jj + g) * ld + rowc) * 8);
+        sreg[j][jj] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)o, 0, 0));
+      }
     }
-    // Block input in D layout: lane (x, g) register r holds W[row x][col g+4r].
-    // Columns past pb lie outside the buffer range and read zero; rows past
-    // m are cleared with a bit mask (values there may be anything).
-    {
-      const uint64_t keep = row_ok ? ~0ull : 0ull;
-      const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+    // block input in D layout: lane (x, g) register r holds W[row x][col
+    // g + 4r]; columns past pb lie outside the buffer range and read zero
+    if (!APPLY || k % WPT == mem) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // columns 4r..4r+3 from base column 4r; lane offset (g ldw + row) * 8
-        const int64_t nrec = (a.pb - 1 >= 4 * r) ? (((int64_t)(a.pb - 1 - 4 * r) * a.ldw + a.m) * 8) : 0;
-        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(4 * r) * a.ldw, nrec);
-        const uint64_t bits = __builtin_bit_cast(uint64_t,
-            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
-        w[r] = __builtin_bit_cast(double, bits & keep);
+        const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
+        w[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
       }
     }
   };
+  auto masked = [](double v, uint64_t keep) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep);
+  };
 
-  // Step k handles row tile t0 + k*G + grp of this workgroup; every wave runs
-  // the same number of steps (barriers), a group past the range works on a
-  // clamped tile with its Y forced to zero and no stores.
-  double snext[NTW][4];
-  d4 wnext;
-  load_tile(min(t0 + grp, t1 - 1), snext, wnext);
-  int it = 0;
-  for (int64_t t = t0; t < t1; t += G, ++it) {
-    const int64_t tile = t + grp;
+  auto do_step = [&](int k, const double (&sreg)[NTW][4], const d4& wraw, uint64_t keep) {
+    const int64_t tile = t0 + (int64_t)k * G + grp;
     const bool tile_ok = tile < t1;
     const int64_t row = tile * 16 + x;
-    const bool row_ok = tile_ok && row < a.m;
-    double sreg[NTW][4];
-#pragma unroll
-    for (int j = 0; j < NTW; ++j)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) sreg[j][jj] = snext[j][jj];
-    const d4 w = wnext;
-    // prefetch this group's next row tile (clamped to a valid tile)
-    load_tile(min(tile + G, t1 - 1), snext, wnext);
+    const bool row_ok = keep != 0;
+    const bool own = k % WPT == mem;     // wave-uniform
     d4 y;
     if (APPLY) {
       // Partial Y^T over my slices (two chains): Y_J = W_J D_J + S C_J with
-      // C_J = -B~_J D_J.  Member 0 adds D^T W^T: register r of W^T (D layout)
-      // is the B operand of k-slice r.
+      // C_J = -B~_J D_J.  The owner adds D^T W^T: register r of W^T (D
+      // layout) is the B operand of k-slice r.
       d4 c0 = d4{0.0, 0.0, 0.0, 0.0};
       d4 c1 = d4{0.0, 0.0, 0.0, 0.0};
-      if (mem == 0) {
-        c0 = mfma(cop[kCop + (g + 0) * 16 + x], w[0], c0);
-        c1 = mfma(cop[kCop + (g + 4) * 16 + x], w[1], c1);
-        c0 = mfma(cop[kCop + (g + 8) * 16 + x], w[2], c0);
-        c1 = mfma(cop[kCop + (g + 12) * 16 + x], w[3], c1);
+      if (own) {
+        c0 = mfma(cop[kCop + (g + 0) * 16 + x], masked(wraw[0], keep), c0);
+        c1 = mfma(cop[kCop + (g + 4) * 16 + x], masked(wraw[1], keep), c1);
+        c0 = mfma(cop[kCop + (g + 8) * 16 + x], masked(wraw[2], keep), c0);
+        c1 = mfma(cop[kCop + (g + 12) * 16 + x], masked(wraw[3], keep), c1);
       }
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
@@ -241,20 +236,20 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
       }
       y = c0 + c1;
       if (WPT > 1) {
-        double* tp = tpart + ((it & 1) * kWaves + wave) * kTPart;
+        double* tp = tpart + ((k & 1) * kWaves + wave) * kTPart;
 #pragma unroll
         for (int r = 0; r < 4; ++r) tp[r * 64 + lane] = y[r];
         __syncthreads();
         // Y^T = sum of the group's partials in member order.
         y = d4{0.0, 0.0, 0.0, 0.0};
-        const double* tb = tpart + ((it & 1) * kWaves + grp * WPT) * kTPart;
+        const double* tb = tpart + ((k & 1) * kWaves + grp * WPT) * kTPart;
 #pragma unroll
         for (int v = 0; v < WPT; ++v)
 #pragma unroll
           for (int r = 0; r < 4; ++r) y[r] += tb[v * kTPart + r * 64 + lane];
       }
       if (!row_ok) y = d4{0.0, 0.0, 0.0, 0.0};
-      if (mem == 0 && tile_ok) {
+      if (own && tile_ok) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = g + 4 * r;
@@ -262,8 +257,8 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
         }
       }
     } else {
-      y = w;
-      if (!tile_ok) y = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[r] = masked(wraw[r], keep);
     }
     // Y through wave-private LDS: the row index becomes the contraction index
     // (k-slot g of slice u <-> row g + 4u).
@@ -274,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) yb[u] = tr[(g + 4 * u) * kYPitch + x];
     wave_lds_sync();
-    if (mem == 0) {
+    if (own) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) accg = mfma(yb[u], yb[u], accg);
     }
@@ -291,6 +286,36 @@ __global__ __launch_bounds__(kThreads) void block_pass(BlockPassArgs a) {
       wave_lds_sync();
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[j] = mfma(sa[u], yb[u], acc[j]);
+    }
+  };
+
+  // Two register buffers: the loads of step k + 1 land in one while step k
+  // computes on the other (no copies, so no wait for the loads in flight).
+  double sb0[NTW][4], sb1[NTW][4];
+  d4 wb0 = d4{0.0, 0.0, 0.0, 0.0}, wb1 = d4{0.0, 0.0, 0.0, 0.0};
+  uint64_t kb0, kb1;
+  load_step(0, sb0, wb0, kb0);
+  for (int k = 0; k < nsteps; k += 2) {
+    load_step(k + 1, sb1, wb1, kb1);
+    do_step(k, sb0, wb0, kb0);
+    if (k + 1 >= nsteps) break;
+    load_step(k + 2, sb0, wb0, kb0);
+    do_step(k + 1, sb1, wb1, kb1);
+  }
+  if (WPT > 1) {
+    // Y^T Y partials of the members (each over the steps it owned), summed
+    // in member order into member 0 of the group.
+    __syncthreads();
+    double* ga = lds;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ga[wave * kTPart + (g + 4 * r) * 16 + x] = accg[r];
+    __syncthreads();
+    if (mem == 0) {
+      accg = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int v = 0; v < WPT; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accg[r] += ga[(grp * WPT + v) * kTPart + (g + 4 * r) * 16 + x];
     }
   }
 
@@ -377,10 +402,10 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __r
 }
 
 // Offset (in doubles) of block J's partial Gramian inside a reduced slot:
-// block J' holds (q4 + 16 J' + 16) rows of 16 doubles, q4 = q rounded up to 4
-// (rows q..q4-1 belong to the zero padding of S and are ignored).
-__device__ __forceinline__ int64_t e_off(int q4, int J) {
-  return 16 * ((int64_t)J * (q4 + 16) + 8 * (int64_t)J * (J - 1));
+// block J' holds (q16 + 16 J' + 16) rows of 16 doubles, q16 = q rounded up to
+// 16 (rows q..q16-1 belong to the zero padding of S and are ignored).
+__device__ __forceinline__ int64_t e_off(int q16, int J) {
+  return 16 * ((int64_t)J * (q16 + 16) + 8 * (int64_t)J * (J - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -431,15 +456,14 @@ __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
   // zero (buffer range).  Rows past m and tiles past the range (t1) are
   // cleared by the mask `keep` when the tile is used, not at the load, so the
   // loads stay in flight until then.
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win, ((int64_t)(a.n - 1) * a.ldw + a.m) * 8);
   auto load = [&](int64_t tile, d4& w, uint64_t& keep) {
     const int64_t row = min(tile, t1 - 1) * 16 + x;
     keep = (row < a.m && tile < t1) ? ~0ull : 0ull;
     const int64_t rowc = row < a.m ? row : a.m - 1;
-    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t nrec = (a.n - 1 >= 4 * r) ? (((int64_t)(a.n - 1 - 4 * r) * a.ldw + a.m) * 8) : 0;
-      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(4 * r) * a.ldw, nrec);
+      const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
       w[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
     }
   };
@@ -572,18 +596,19 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
     const bool row_ok = row < a.m;
     const int64_t rowc = row_ok ? row : a.m - 1;
     const uint64_t keep = row_ok ? ~0ull : 0ull;
-    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
 #pragma unroll
-    for (int J = 0; J < NB; ++J)
+    for (int J = 0; J < NB; ++J) {
+      // one descriptor per 16-column block
+      const int64_t nrec = (a.n - 1 >= 16 * J) ? (((int64_t)(a.n - 1 - 16 * J) * a.ldw + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(16 * J) * a.ldw, nrec);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c0 = 16 * J + 4 * r;
-        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
-        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+        const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
         const uint64_t bits = __builtin_bit_cast(uint64_t,
             __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
         w[J][r] = __builtin_bit_cast(double, bits & keep);
       }
+    }
   };
 
   d4 acc[G32 ? 1 : KP];
@@ -787,13 +812,13 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
     const bool row_ok = row < a.m;
     const int64_t rowc = row_ok ? row : a.m - 1;
     const uint64_t keep = row_ok ? ~0ull : 0ull;
-    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
+    // one descriptor per 16-column block
+    const int64_t nrec = (a.n - 1 >= 16 * J) ? (((int64_t)(a.n - 1 - 16 * J) * a.ldw + a.m) * 8) : 0;
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(16 * J) * a.ldw, nrec);
     d4 w;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int c0 = 16 * J + 4 * r;
-      const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
-      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+      const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
       const uint64_t bits = __builtin_bit_cast(uint64_t,
           __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
       w[r] = __builtin_bit_cast(double, bits & keep);
@@ -912,18 +937,20 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
     const bool row_ok = row < a.m;
     const int64_t rowc = row_ok ? row : a.m - 1;
     const uint64_t keep = row_ok ? ~0ull : 0ull;
-    const uint32_t ow = (uint32_t)(((int64_t)g * a.ldw + rowc) * 8);
 #pragma unroll
-    for (int jj = 0; jj < H; ++jj)
+    for (int jj = 0; jj < H; ++jj) {
+      // one descriptor per 16-column block
+      const int c0 = 16 * (half * H + jj);
+      const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c0 = 16 * (half * H + jj) + 4 * r;
-        const int64_t nrec = (a.n - 1 >= c0) ? (((int64_t)(a.n - 1 - c0) * a.ldw + a.m) * 8) : 0;
-        const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)c0 * a.ldw, nrec);
+        const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
         const uint64_t bits = __builtin_bit_cast(uint64_t,
             __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
         w[jj][r] = __builtin_bit_cast(double, bits & keep);
       }
+    }
   };
 
   Acc acc[KP];
@@ -1378,14 +1405,14 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
 
   // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
   //    G = E[q:q+p, :] (upper, mirrored).
-  const int q4 = (q + 3) & ~3;
+  const int q16 = (q + 15) & ~15;
   const double* E = a.E;
   fill_rows(X, p, p, [&](int i, int j) {
     const int lo = min(i, j), hi = max(i, j);
-    return E[e_off(q4, hi >> 4) + (int64_t)(q4 + lo) * 16 + (hi & 15)];
+    return E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
   });
   fill_rows(Bt, q, p, [&](int i, int j) {
-    return E[e_off(q4, j >> 4) + (int64_t)i * 16 + (j & 15)];
+    return E[e_off(q16, j >> 4) + (int64_t)i * 16 + (j & 15)];
   });
   // old diagonal block of R and old B, loaded together with the Gramian
   // blocks (at phase 0 they are the identity and zero: step 6 then copies)
@@ -1856,20 +1883,20 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
   if (a.nblk <= kLdsDBlocks)
     for (int e = tid; e < a.nblk * 256; e += kSmallThreads) vw[e] = a.rinv[e];
   wg_sync(a.nblk <= kLdsDBlocks);
-  //    C_J = -[B~[:, J]; 0 (padding rows q..q4-1); R~[0:16J, J]] D_J, so the
+  //    C_J = -[B~[:, J]; 0 (padding rows q..q16-1); R~[0:16J, J]] D_J, so the
   //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
   //    One row of C_J per thread: the row of the source in registers, D_J
   //    read as broadcasts.
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
-    const int rows = q4 + b0;
+    const int rows = q16 + b0;
     const double* D = (a.nblk <= kLdsDBlocks) ? vw + J * 256 : a.rinv + J * 256;
-    double* bn = a.bneg + 16 * ((int64_t)J * q4 + 8 * (int64_t)J * (J - 1));
+    double* bn = a.bneg + 16 * ((int64_t)J * q16 + 8 * (int64_t)J * (J - 1));
     for (int kk = tid; kk < rows; kk += kSmallThreads) {
       double src[16];
-      const bool real = kk < q || kk >= q4;
+      const bool real = kk < q || kk >= q16;
       const double* sr = (kk < q) ? Bt + (int64_t)kk * p + b0
-                                  : (real ? M + (int64_t)(kk - q4) * p + b0 : Bt);
+                                  : (real ? M + (int64_t)(kk - q16) * p + b0 : Bt);
 #pragma unroll
       for (int t = 0; t < 16; ++t) src[t] = (real && t < pb) ? sr[t] : 0.0;
 #pragma unroll

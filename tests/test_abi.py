@@ -141,3 +141,12 @@ def test_noalloc_usage_errors_and_limit_before_any_gpu_work(sq):
     assert _noalloc(sq, 10000, maxc + 1, 10000, 10000, maxc + 1) == sq.SQR_ELIMIT
     bad = sq.sqr_default_opts(max_iter=0)
     assert _noalloc(sq, 100, 10, 100, 100, 10, opts=bad) == sq.SQR_EOPT
+
+
+def test_leading_dimension_limit(sq):
+    """Leading dimensions of 2^25 rows or more are refused (lane offsets
+    inside a 16-column tile must stay below 4 GiB)."""
+    big = 1 << 25
+    assert _orth(sq, 100, 10, big, 100, 10, 10) == sq.SQR_EDIM
+    assert _orth(sq, 100, 10, 100, big, 10, 10) == sq.SQR_EDIM
+    assert _noalloc(sq, 100, 10, big, 100, 10) == sq.SQR_EDIM
