@@ -51,6 +51,17 @@ class SqrInfo(ctypes.Structure):
                     orth_fro=self.orth_fro, sigma=list(self.sigma[:n]))
 
 
+class SqrBatchItem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rc", ctypes.c_int32), ("basis", ctypes.c_void_p),
+                ("inp", ctypes.c_void_p), ("ld_in", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("cap", ctypes.c_int64), ("Q", ctypes.c_void_p),
+                ("ldq", ctypes.c_int64), ("R", ctypes.c_void_p), ("ldr", ctypes.c_int64),
+                ("info", SqrInfo)]
+
+
+SQR_BATCH_ORTH, SQR_BATCH_APPEND = 0, 1
+
+
 class SqrProf(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 2), ("ms", ctypes.c_double * 2),
                 ("bytes", ctypes.c_double * 2)]
@@ -70,6 +81,8 @@ def _load():
     lib.sqr_orth_noalloc.argtypes = [ctypes.POINTER(SqrOpts), I64, I64, P, I64, P, I64,
                                      P, I64, P, ctypes.POINTER(SqrInfo)]
     lib.sqr_orth_noalloc.restype = I32
+    lib.sqr_batch.argtypes = [ctypes.POINTER(SqrOpts), ctypes.POINTER(SqrBatchItem), ctypes.c_int32, P]
+    lib.sqr_batch.restype = I32
     lib.sqr_append.argtypes = [P, P, I64, I64, P, ctypes.POINTER(SqrInfo)]
     lib.sqr_append.restype = I32
     lib.sqr_last_info.argtypes = [P, ctypes.POINTER(SqrInfo)]
@@ -211,6 +224,45 @@ def sqr_append(b: Basis, W: torch.Tensor, stream=None) -> dict:
     if rc < 0:
         raise RuntimeError(f"sqr_append failed with code {rc}")
     return info.as_dict()
+
+
+def sqr_batch(calls, opts: SqrOpts | None = None, stream=None) -> list:
+    """Run several calls together (sqr_batch): each entry is
+    ``("orth", A, cap, Q, R)`` or ``("append", basis, W)``.  Returns, per
+    call, a dict with ``rc`` (as sqr_orth / sqr_append return it), ``info``
+    and, for an orthogonalisation that ran, its ``basis``.  Raises ValueError
+    on inconsistent shapes or devices before the library is called."""
+    items = (SqrBatchItem * len(calls))()
+    keep = []
+    for it, call in zip(items, calls):
+        if call[0] == "orth":
+            _, A, cap, Q, R = call
+            if A.dim() != 2:
+                raise ValueError("A must be a matrix")
+            m, n = A.shape
+            _check_matrix("Q", Q, m, cap, A.device)
+            _check_matrix("R", R, cap, cap, A.device)
+            it.kind, it.inp, it.ld_in, it.m, it.cols, it.cap = SQR_BATCH_ORTH, A.data_ptr(), _ld(A), m, n, cap
+            it.Q, it.ldq, it.R, it.ldr = Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R)
+            keep.append((A, Q, R))
+        elif call[0] == "append":
+            _, b, W = call
+            _check_matrix("W", W, b.m, 1, b.Q.device)
+            it.kind, it.basis, it.inp, it.ld_in, it.cols = SQR_BATCH_APPEND, b.handle.value, W.data_ptr(), _ld(W), W.shape[1]
+            keep.append((W,))
+        else:
+            raise ValueError(f"unknown call kind {call[0]!r}")
+    rc = lib.sqr_batch(ctypes.byref(opts) if opts is not None else None, items, len(calls), _stream(stream))
+    if rc in (SQR_ENULL, SQR_EOPT):
+        raise RuntimeError(f"sqr_batch failed with code {rc}")
+    out = []
+    for it, call in zip(items, calls):
+        d = {"rc": it.rc, "info": it.info.as_dict()}
+        if call[0] == "orth" and it.rc >= 0 and it.basis:
+            _, A, cap, Q, R = call
+            d["basis"] = Basis(ctypes.c_void_p(it.basis), Q, R, A.shape[0], cap)
+        out.append(d)
+    return out
 
 
 def sqr_last_info(b: Basis) -> dict:

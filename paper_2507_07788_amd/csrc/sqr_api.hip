@@ -26,6 +26,7 @@
 
 #include "../../include/sqr.h"
 #include "../../include/sqr_prof.h"
+#include "../../include/sqr_batch.h"
 
 #include "sqr_kernels.hip"
 
@@ -166,12 +167,16 @@ struct sqr_basis {
 namespace {
 
 typedef void (*BlockKernel)(BlockPassArgs);
+typedef void (*BlockBatchKernel)(BatchTable<BlockPassArgs>);
 // nt = S tiles per wave, wpt = waves sharing a row tile (4 / wpt row tiles
-// in flight per workgroup); a variant covers nt * wpt tiles of S.
-struct Variant { int nt, wpt; BlockKernel gram, apply; };
+// in flight per workgroup); a variant covers nt * wpt tiles of S.  Every
+// kernel comes with its batched form (the same work for several calls in one
+// launch).
+struct Variant { int nt, wpt; BlockKernel gram, apply; BlockBatchKernel gram_b, apply_b; };
 int g_occ[2][32];     // workgroups per CU of each variant (gram, apply)
 int g_ncu = 0;
-#define SQR_VARIANT(NT, W) {NT, W, block_pass<NT, W, false>, block_pass<NT, W, true>}
+#define SQR_VARIANT(NT, W) {NT, W, block_pass<NT, W, false>, block_pass<NT, W, true>, \
+                            block_pass_batch<NT, W, false>, block_pass_batch<NT, W, true>}
 const Variant kVariants[] = {
   SQR_VARIANT(1, 1), SQR_VARIANT(1, 2), SQR_VARIANT(2, 2),
   SQR_VARIANT(2, 4), SQR_VARIANT(3, 4), SQR_VARIANT(4, 4), SQR_VARIANT(5, 4),
@@ -182,9 +187,12 @@ const Variant kVariants[] = {
 // Whole-pass kernels of orth calls with up to 8 column blocks (FP64 calls use
 // them from 2 blocks on; the mixed form from 1), with FP64 or FP32 Gramians.
 typedef void (*WideKernel)(WidePassArgs);
-struct WideVariant { WideKernel k[2][2]; };   // [fp32 gram][apply]
+typedef void (*WideBatchKernel)(BatchTable<WidePassArgs>);
+struct WideVariant { WideKernel k[2][2]; WideBatchKernel kb[2][2]; };   // [fp32 gram][apply]
 #define SQR_WIDE(NB) {{{wide_pass<NB, false, false>, wide_pass<NB, true, false>}, \
-                       {wide_pass<NB, false, true>, wide_pass<NB, true, true>}}}
+                       {wide_pass<NB, false, true>, wide_pass<NB, true, true>}}, \
+                      {{wide_pass_batch<NB, false, false>, wide_pass_batch<NB, true, false>}, \
+                       {wide_pass_batch<NB, false, true>, wide_pass_batch<NB, true, true>}}}
 constexpr int kWideMin = 1, kWideMax = 8;
 const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
                              SQR_WIDE(5), SQR_WIDE(6), SQR_WIDE(7), SQR_WIDE(8)};
@@ -193,13 +201,15 @@ int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 
 // FP64 orth calls of one block (at most 16 columns): [Gram only, apply].
 const WideKernel kNarrow[2] = {narrow_pass<false>, narrow_pass<true>};
+const WideBatchKernel kNarrowB[2] = {narrow_pass_batch<false>, narrow_pass_batch<true>};
 int g_narrow_occ[2];
 
 // Orth calls of 8..16 blocks: a whole-pass apply and a Gramian kernel
 // (FP64, and FP32 for the mixed form).
 typedef void (*SplitKernel)(WidePassArgs);
-struct SplitVariant { SplitKernel apply, gram, gram32; };
-#define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB, false>, gram_pass<NB, true>}
+struct SplitVariant { SplitKernel apply, gram, gram32; WideBatchKernel apply_b, gram_b, gram32_b; };
+#define SQR_SPLIT(NB) {wide_apply<NB>, gram_pass<NB, false>, gram_pass<NB, true>, \
+                       wide_apply_batch<NB>, gram_pass_batch<NB, false>, gram_pass_batch<NB, true>}
 constexpr int kSplitMin = 8, kSplitMax = 16;
 const SplitVariant kSplit[] = {SQR_SPLIT(8), SQR_SPLIT(9), SQR_SPLIT(10), SQR_SPLIT(11), SQR_SPLIT(12),
                                SQR_SPLIT(13), SQR_SPLIT(14), SQR_SPLIT(15), SQR_SPLIT(16)};
@@ -232,28 +242,36 @@ size_t block_lds_bytes(const Variant& v, bool apply) {
 // serving loop calls the library from several threads at once).
 std::once_flag g_attr_once;
 void set_kernel_attributes_once() {
+  auto lds_attr = [](const void* k, int bytes) {
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
   for (const Variant& v : kVariants) {
-    (void)hipFuncSetAttribute((const void*)v.gram, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
-    (void)hipFuncSetAttribute((const void*)v.apply, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+    lds_attr((const void*)v.gram, 120 * 1024);
+    lds_attr((const void*)v.apply, 120 * 1024);
+    lds_attr((const void*)v.gram_b, 120 * 1024);
+    lds_attr((const void*)v.apply_b, 120 * 1024);
   }
   if (hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kSmallLdsBytes) != hipSuccess ||
+      hipFuncSetAttribute((const void*)small_step_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kSmallLdsBytes) != hipSuccess) {
     (void)hipGetLastError();   // consumed here: arenas then live in the workspace
     g_small_lds = 0;
   }
   for (int nb = kWideMin; nb <= kWideMax; ++nb)
     for (int g32 = 0; g32 < 2; ++g32)
-      for (int ap = 0; ap < 2; ++ap)
-        (void)hipFuncSetAttribute((const void*)kWide[nb - kWideMin].k[g32][ap],
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)wide_lds_bytes(nb, ap != 0));
+      for (int ap = 0; ap < 2; ++ap) {
+        lds_attr((const void*)kWide[nb - kWideMin].k[g32][ap], (int)wide_lds_bytes(nb, ap != 0));
+        lds_attr((const void*)kWide[nb - kWideMin].kb[g32][ap], (int)wide_lds_bytes(nb, ap != 0));
+      }
   for (int nb = kSplitMin; nb <= kSplitMax; ++nb) {
-    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].apply,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, true));
-    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].gram,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_lds_bytes(nb, false));
-    (void)hipFuncSetAttribute((const void*)kSplit[nb - kSplitMin].gram32,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram32_lds_bytes(nb));
+    const SplitVariant& v = kSplit[nb - kSplitMin];
+    lds_attr((const void*)v.apply, (int)split_lds_bytes(nb, true));
+    lds_attr((const void*)v.gram, (int)split_lds_bytes(nb, false));
+    lds_attr((const void*)v.gram32, (int)gram32_lds_bytes(nb));
+    lds_attr((const void*)v.apply_b, (int)split_lds_bytes(nb, true));
+    lds_attr((const void*)v.gram_b, (int)split_lds_bytes(nb, false));
+    lds_attr((const void*)v.gram32_b, (int)gram32_lds_bytes(nb));
   }
   (void)hipGetLastError();
   int dev = 0;
@@ -410,16 +428,56 @@ struct Call {
 
 int variant_index(const Variant* v) { return (int)(v - kVariants); }
 
-int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
+// One kernel launch of a pass, with its single-call and batched kernels.
+struct Launch {
+  enum Kind { kBlock, kWide, kReduce, kSmall } kind;
+  const void* k1;          // kernel of one call (arguments by value)
+  const void* kb;          // the same kernel for a batch of calls
+  union {
+    BlockPassArgs bp;
+    WidePassArgs wp;
+    ReduceArgs ra;
+    SmallArgs sa;
+  } u;
+  int64_t grid;            // workgroups of this call
+  int threads;
+  size_t lds;              // dynamic LDS bytes
+  int prof_kind;           // streaming step record: 0 Gram, 1 apply, -1 none
+  double prof_bytes;       // algorithmic bytes of the record
+  bool prof_join;          // belongs to the previous launch's record
+};
+
+size_t launch_arg_bytes(Launch::Kind k) {
+  switch (k) {
+    case Launch::kBlock: return sizeof(BlockPassArgs);
+    case Launch::kWide: return sizeof(WidePassArgs);
+    case Launch::kReduce: return sizeof(ReduceArgs);
+    default: return sizeof(SmallArgs);
+  }
+}
+
+// The launches of pass `phase` of a call, in order: the streaming kernels
+// (by route), the fixed-order reduction of the slots, the small step.
+int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
   const int64_t P = nblocks(c.p);
   const int64_t tl = total_len(c.q, c.p);
   const int64_t tiles = (b->m + 15) / 16;
   const bool apply = phase > 0;
   int64_t nwg = b->slots;
   const bool mixed = c.mode == 0 && b->opts.precision == 1;
+  auto push_wide = [&](const void* k1, const void* kb, const WidePassArgs& w, int64_t grid, int threads,
+                       size_t lds, int kind, double bytes, bool join) {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kWide; L.k1 = k1; L.kb = kb; L.u.wp = w;
+    L.grid = grid; L.threads = threads; L.lds = lds;
+    L.prof_kind = kind; L.prof_bytes = bytes; L.prof_join = join;
+    out.push_back(L);
+  };
   if (c.mode == 0 && P >= kSplitMin && P <= kSplitMax && (!mixed || P > kWideMax)) {
     // apply (from pass 1 on), then the Gramian of its result
     const int idx = (int)P - kSplitMin;
+    const SplitVariant& sv = kSplit[idx];
     const int64_t steps = (tiles + kWaves - 1) / kWaves;
     WidePassArgs w;
     memset(&w, 0, sizeof(w));
@@ -428,33 +486,19 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.part = b->part; w.part_stride = tl;
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
-    auto launch = [&](const void* k, int64_t grid, int threads, size_t lds) {
-      void* args[] = {&w};
-      return hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), args, lds, s) == hipSuccess;
-    };
-    // launches between one pair of profiling events (the mixed form's two
-    // Gramian variants count as one launch: one of them exits at once)
-    auto timed = [&](int kind, double bytes, auto&& enqueue) {
-      const ProfRec rec = prof_begin(kind, bytes, b->noprof ? -1 : b->call_id, phase, s);
-      if (!enqueue()) return false;
-      prof_end(rec, s);
-      return true;
-    };
     if (apply) {
       w.win = (phase > 1) ? c.y : c.win;
       w.ldw = (phase > 1) ? c.ldy : c.ldw;
       w.yout = c.y; w.ldy = c.ldy;
       w.copy_if_done = (phase == 1);
       const int64_t ga = std::max<int64_t>(1, std::min<int64_t>((int64_t)g_ncu * g_split_occ[1][idx], steps));
-      if (!timed(1, 16.0 * (double)b->m * (double)c.p, [&] {
-            return launch((const void*)kSplit[idx].apply, ga, kThreads, split_lds_bytes((int)P, true));
-          }))
-        return SQR_EHIP;
+      push_wide((const void*)sv.apply, (const void*)sv.apply_b, w, ga, kThreads, split_lds_bytes((int)P, true),
+                1, 16.0 * (double)b->m * (double)c.p, false);
     }
     // the Gramian of the pass's result (of the input at phase 0); the mixed
     // form launches the FP32 variant at phase 0 and both variants later, the
     // one that does not match the device's choice (ctrl->gram32) exits at
-    // once.  Both fill the same nwg slots.
+    // once.  Both fill the same nwg slots and count as one measured launch.
     w.win = apply ? c.y : c.win;
     w.ldw = apply ? c.ldy : c.ldw;
     w.copy_if_done = 0;
@@ -462,13 +506,13 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
     nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, steps));
     w.gram32 = (mixed && phase > 0) ? &b->ctrl->gram32 : nullptr;
-    if (!timed(0, 8.0 * (double)b->m * (double)c.p, [&] {
-          if (mixed && !launch((const void*)kSplit[idx].gram32, nwg, kGramThreads, gram32_lds_bytes((int)P)))
-            return false;
-          return (mixed && phase == 0) ||
-                 launch((const void*)kSplit[idx].gram, nwg, kGramThreads, split_lds_bytes((int)P, false));
-        }))
-      return SQR_EHIP;
+    const double gb = 8.0 * (double)b->m * (double)c.p;
+    if (mixed)
+      push_wide((const void*)sv.gram32, (const void*)sv.gram32_b, w, nwg, kGramThreads, gram32_lds_bytes((int)P),
+                0, gb, false);
+    if (!(mixed && phase == 0))
+      push_wide((const void*)sv.gram, (const void*)sv.gram_b, w, nwg, kGramThreads, split_lds_bytes((int)P, false),
+                0, gb, mixed);
   } else if (c.mode == 0 && P == 1 && !mixed) {
     // one block: the whole pass in one launch, every wave on its own tiles
     nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_narrow_occ[apply ? 1 : 0]);
@@ -484,13 +528,8 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
     w.copy_if_done = (phase == 1);
-    void* args[] = {&w};
-    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
-                                   b->noprof ? -1 : b->call_id, phase, s);
-    if (hipLaunchKernel((const void*)kNarrow[apply ? 1 : 0], dim3((unsigned)nwg), dim3(kThreads), args, 0, s) !=
-        hipSuccess)
-      return SQR_EHIP;
-    prof_end(rec, s);
+    push_wide((const void*)kNarrow[apply ? 1 : 0], (const void*)kNarrowB[apply ? 1 : 0], w, nwg, kThreads, 0,
+              apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0), false);
   } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
     // precision from pass 1 on; the one that does not match the device's
@@ -511,88 +550,126 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
     w.copy_if_done = (phase == 1);
-    void* args[] = {&w};
-    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0),
-                                   b->noprof ? -1 : b->call_id, phase, s);
+    const double bytes = 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0);
+    bool join = false;
     for (int g32 = mixed ? 1 : 0; g32 >= 0; --g32) {
       // phase 0 of the mixed form is an FP32 Gramian; later phases follow the
       // device (ctrl->gram32); FP64 calls launch the FP64 variant only
       if (mixed && phase == 0 && g32 == 0) break;
       w.gram32 = (mixed && phase > 0) ? &b->ctrl->gram32 : nullptr;
-      const WideKernel k = kWide[idx].k[g32][apply ? 1 : 0];
-      if (hipLaunchKernel((const void*)k, dim3((unsigned)nwg), dim3(kThreads), args,
-                          wide_lds_bytes((int)P, apply), s) != hipSuccess)
+      push_wide((const void*)kWide[idx].k[g32][apply ? 1 : 0], (const void*)kWide[idx].kb[g32][apply ? 1 : 0], w,
+                nwg, kThreads, wide_lds_bytes((int)P, apply), apply ? 1 : 0, bytes, join);
+      join = true;
+    }
+  } else {
+    // One grid size for every block of the pass (the slots are reduced
+    // together): resident workgroups of the most demanding block's variant,
+    // capped by the slot capacity and by the row tiles available.
+    for (int64_t J = 0; J < P; ++J) {
+      const int ks = (int)round16(c.q) + (int)(16 * J);
+      const Variant* v = pick_variant((ks + 15) / 16);
+      if (!v) return SQR_EDIM;
+      const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
+      nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
+      nwg = std::min<int64_t>(nwg, (tiles + (kWaves / v->wpt) - 1) / (kWaves / v->wpt));
+    }
+    nwg = std::max<int64_t>(nwg, 1);
+    for (int64_t J = 0; J < P; ++J) {
+      Launch L;
+      memset(&L, 0, sizeof(L));
+      BlockPassArgs& a = L.u.bp;
+      const double* src = (apply && phase > 1) ? c.y : c.win;
+      const int64_t lds = (apply && phase > 1) ? c.ldy : c.ldw;
+      a.win = src + J * 16 * lds; a.ldw = lds;
+      a.yout = c.y + J * 16 * c.ldy; a.ldy = c.ldy;
+      a.s1 = b->Q; a.ld1 = b->ldq; a.n1 = (int)c.q;
+      // same-pass prefix: new values after an apply, the input for the first Gram
+      a.s2 = apply ? c.y : c.win; a.ld2 = apply ? c.ldy : c.ldw; a.n2 = (int)(16 * J);
+      a.pb = (int)std::min<int64_t>(16, c.p - 16 * J);
+      a.m = b->m;
+      a.bneg = b->bneg + bneg_off(c.q, J);
+      a.rinv = b->rinv + 256 * J;
+      a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
+      a.done = phase > 0 ? &b->ctrl->done : nullptr;  // phase 0 starts the call
+      a.passes = &b->ctrl->passes;
+      a.copy_if_done = (phase == 1);
+      const int ks = (int)round16(a.n1) + a.n2;   // columns of S with the padding
+      const Variant* v = pick_variant((ks + 15) / 16);
+      L.kind = Launch::kBlock;
+      L.k1 = (const void*)(apply ? v->apply : v->gram);
+      L.kb = (const void*)(apply ? v->apply_b : v->gram_b);
+      L.grid = nwg; L.threads = kThreads; L.lds = block_lds_bytes(*v, apply);
+      // algorithmic bytes: the real columns of S (no padding), the block read,
+      // and (apply) the block written
+      L.prof_kind = apply ? 1 : 0;
+      L.prof_bytes = 8.0 * (double)b->m * (double)(a.n1 + a.n2 + (apply ? 2 : 1) * a.pb);
+      out.push_back(L);
+    }
+  }
+  {
+    // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kReduce; L.k1 = (const void*)reduce_slots; L.kb = (const void*)reduce_slots_batch;
+    ReduceArgs& r = L.u.ra;
+    r.in = b->part; r.nslots = (int)nwg; r.stride = tl; r.len = tl; r.out = b->stage;
+    r.done = phase > 0 ? &b->ctrl->done : nullptr;
+    L.grid = (tl + kRedElems - 1) / kRedElems; L.threads = 64 * kRedWaves; L.lds = 0;
+    L.prof_kind = -1;
+    out.push_back(L);
+  }
+  {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kSmall; L.k1 = (const void*)small_step; L.kb = (const void*)small_step_batch;
+    SmallArgs& k = L.u.sa;
+    k.E = b->stage;
+    k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+    k.m = b->m; k.phase = phase;
+    k.R = b->R; k.ldr = b->ldr;
+    k.X = b->X;
+    k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+    k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256;
+    k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
+    k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
+    k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+    k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
+    k.mixed = mixed ? 1 : 0;
+    const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
+    const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
+    k.lds_matrices = (arena <= g_small_lds) ? 1 : (mbytes <= g_small_lds ? 2 : 0);
+    L.lds = k.lds_matrices == 1 ? arena : (k.lds_matrices == 2 ? mbytes : 0);
+    L.grid = 1; L.threads = kSmallThreads;
+    L.prof_kind = -1;
+    out.push_back(L);
+  }
+  return SQR_OK;
+}
+
+// Enqueue the launches of one call's pass on s, with the measurement records.
+int exec_single(sqr_basis* b, int phase, const std::vector<Launch>& L, hipStream_t s) {
+  for (size_t i = 0; i < L.size();) {
+    size_t j = i + 1;   // launches i .. j-1 share one measurement record
+    if (L[i].prof_kind >= 0)
+      while (j < L.size() && L[j].prof_join) ++j;
+    ProfRec rec{};
+    if (L[i].prof_kind >= 0) rec = prof_begin(L[i].prof_kind, L[i].prof_bytes, b->noprof ? -1 : b->call_id, phase, s);
+    for (size_t k = i; k < j; ++k) {
+      void* args[] = {(void*)&L[k].u};
+      if (hipLaunchKernel(L[k].k1, dim3((unsigned)L[k].grid), dim3(L[k].threads), args, L[k].lds, s) != hipSuccess)
         return SQR_EHIP;
     }
-    prof_end(rec, s);
-  } else {
-  // One grid size for every block of the pass (the slots are reduced
-  // together): resident workgroups of the most demanding block's variant,
-  // capped by the slot capacity and by the row tiles available.
-  for (int64_t J = 0; J < P; ++J) {
-    const int ks = (int)round16(c.q) + (int)(16 * J);
-    const Variant* v = pick_variant((ks + 15) / 16);
-    if (!v) return SQR_EDIM;
-    const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
-    nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
-    nwg = std::min<int64_t>(nwg, (tiles + (kWaves / v->wpt) - 1) / (kWaves / v->wpt));
+    if (L[i].prof_kind >= 0) prof_end(rec, s);
+    i = j;
   }
-  nwg = std::max<int64_t>(nwg, 1);
-  for (int64_t J = 0; J < P; ++J) {
-    BlockPassArgs a;
-    memset(&a, 0, sizeof(a));
-    const double* src = (apply && phase > 1) ? c.y : c.win;
-    const int64_t lds = (apply && phase > 1) ? c.ldy : c.ldw;
-    a.win = src + J * 16 * lds; a.ldw = lds;
-    a.yout = c.y + J * 16 * c.ldy; a.ldy = c.ldy;
-    a.s1 = b->Q; a.ld1 = b->ldq; a.n1 = (int)c.q;
-    // same-pass prefix: new values after an apply, the input for the first Gram
-    a.s2 = apply ? c.y : c.win; a.ld2 = apply ? c.ldy : c.ldw; a.n2 = (int)(16 * J);
-    a.pb = (int)std::min<int64_t>(16, c.p - 16 * J);
-    a.m = b->m;
-    a.bneg = b->bneg + bneg_off(c.q, J);
-    a.rinv = b->rinv + 256 * J;
-    a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
-    a.done = phase > 0 ? &b->ctrl->done : nullptr;  // phase 0 starts the call
-    a.passes = &b->ctrl->passes;
-    a.copy_if_done = (phase == 1);
-    const int ks = (int)round16(a.n1) + a.n2;   // columns of S with the padding
-    const Variant* v = pick_variant((ks + 15) / 16);
-    void* args[] = {&a};
-    // algorithmic bytes: the real columns of S (no padding), the block read,
-    // and (apply) the block written
-    const ProfRec rec = prof_begin(apply ? 1 : 0, 8.0 * (double)b->m * (double)(a.n1 + a.n2 + (apply ? 2 : 1) * a.pb),
-                                   b->noprof ? -1 : b->call_id, phase, s);
-    if (hipLaunchKernel((const void*)(apply ? v->apply : v->gram), dim3((unsigned)nwg),
-                        dim3(kThreads), args, block_lds_bytes(*v, apply), s) != hipSuccess)
-      return SQR_EHIP;
-    prof_end(rec, s);
-  }
-  }
-  // Fixed-order reduction of the nwg slots into the pass's Gramian blocks.
-  hipLaunchKernelGGL(reduce_slots, dim3((unsigned)((tl + kRedElems - 1) / kRedElems)), dim3(64 * kRedWaves), 0, s,
-                     (const double*)b->part, (int)nwg, tl, tl, b->stage,
-                     phase > 0 ? (const int*)&b->ctrl->done : (const int*)nullptr);
-  SmallArgs k;
-  memset(&k, 0, sizeof(k));
-  k.E = b->stage;
-  k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
-  k.m = b->m; k.phase = phase;
-  k.R = b->R; k.ldr = b->ldr;
-  k.X = b->X;
-  k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
-  k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256;
-  k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
-  k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
-  k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
-  k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
-  k.mixed = mixed ? 1 : 0;
-  const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
-  const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
-  k.lds_matrices = (arena <= g_small_lds) ? 1 : (mbytes <= g_small_lds ? 2 : 0);
-  const size_t dyn = k.lds_matrices == 1 ? arena : (k.lds_matrices == 2 ? mbytes : 0);
-  hipLaunchKernelGGL(small_step, dim3(1), dim3(kSmallThreads), dyn, s, k);
-  return hipGetLastError() == hipSuccess ? SQR_OK : SQR_EHIP;
+  return SQR_OK;
+}
+
+int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
+  std::vector<Launch> L;
+  int rc = plan_pass(b, c, phase, L);
+  if (rc) return rc;
+  return exec_single(b, phase, L, s);
 }
 
 int fetch(sqr_basis* b, hipStream_t s) {
@@ -640,11 +717,12 @@ void fill_info(const Ctrl* c, sqr_info* info) {
 
 // Run one call.  sync: enqueue `spec` passes, then add passes one by one while
 // the device reports neither convergence nor failure.
-int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
+// A call of the handle on stream s starts after all work of its previous
+// call: kernels of that call (no-op launches of a finished call among them)
+// may still be queued on its stream and read the control block that the new
+// call resets, so s waits for an event recorded there.
+int order_after_previous(sqr_basis* b, hipStream_t s) {
   if (b->used && s != b->stream) {
-    // Kernels of the previous call (no-op launches of a finished call among
-    // them) may still be queued on its stream and read the control block
-    // that this call resets: this stream waits for all of them.
     if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
       b->order_ev = nullptr;
       return SQR_EHIP;
@@ -656,7 +734,13 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   b->used = true;
   b->stream = s;
   b->call_id = ++g_call_id;
-  int rc = launch_gram(b, c, 0, s);
+  return SQR_OK;
+}
+
+int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
+  int rc = order_after_previous(b, s);
+  if (rc) return rc;
+  rc = launch_gram(b, c, 0, s);
   if (rc) return rc;
   const int maxit = b->opts.max_iter;
   int enq = 0;
@@ -670,6 +754,179 @@ int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
     if ((rc = wait_phase(b, s, enq))) return rc;
   }
   if (g_prof_on) prof_finalize(b->call_id, b->ctrl_host->passes);
+  return SQR_OK;
+}
+
+// ---- batched calls (sqr_batch): the passes of several calls advance
+// together; each launch of a pass carries one kernel for every call whose
+// pass uses it at that position (the same route, the same grid per call as
+// alone), reading the calls' argument blocks from a table in device memory.
+// Argument tables are staged in pinned host memory and copied with one
+// transfer per round of passes.
+struct BatchStage {
+  char* host = nullptr;   // pinned
+  char* dev = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+std::mutex g_stage_mu;
+std::vector<BatchStage> g_stages;   // idle staging buffers
+
+BatchStage take_stage(int device, size_t need) {
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (size_t i = 0; i < g_stages.size(); ++i)
+      if (g_stages[i].device == device && g_stages[i].bytes >= need) {
+        BatchStage st = g_stages[i];
+        g_stages.erase(g_stages.begin() + i);
+        return st;
+      }
+  }
+  BatchStage st;
+  const size_t bytes = std::max<size_t>(need, 1 << 20);
+  if (hipHostMalloc((void**)&st.host, bytes, hipHostMallocDefault) != hipSuccess) return BatchStage{};
+  if (hipMalloc((void**)&st.dev, bytes) != hipSuccess) {
+    (void)hipHostFree(st.host);
+    return BatchStage{};
+  }
+  st.bytes = bytes;
+  st.device = device;
+  return st;
+}
+
+void put_stage(const BatchStage& st) {
+  if (!st.host) return;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  g_stages.push_back(st);
+  while (g_stages.size() > 4) {
+    (void)hipHostFree(g_stages.front().host);
+    (void)hipFree(g_stages.front().dev);
+    g_stages.erase(g_stages.begin());
+  }
+}
+
+struct BatchCall {
+  sqr_basis* b;
+  Call c;
+  int enq;      // passes enqueued after the initial Gram pass
+  int spec;     // passes enqueued before the first wait
+};
+
+// Enqueue pass `phase[i]` of every call i in `who` as batched launches.
+// `off` is the running offset into the staging buffers.
+int enqueue_round(std::vector<BatchCall>& calls, const std::vector<int>& who, const std::vector<int>& phase,
+                  BatchStage& st, size_t& off, hipStream_t s) {
+  std::vector<std::vector<Launch>> plans(who.size());
+  size_t maxstream = 0;
+  for (size_t i = 0; i < who.size(); ++i) {
+    BatchCall& bc = calls[who[i]];
+    const int rc = plan_pass(bc.b, bc.c, phase[i], plans[i]);
+    if (rc) return rc;
+    maxstream = std::max(maxstream, plans[i].size() - 2);
+  }
+  struct Group { const void* kb; size_t args_off, start_off; int n; int64_t grid; int threads; size_t lds; };
+  std::vector<Group> groups;
+  const size_t off0 = off;
+  auto align = [&](size_t a) { off = (off + a - 1) / a * a; };
+  // one group per batched kernel at each launch position, in call order
+  auto build = [&](const std::vector<std::pair<size_t, const Launch*>>& members) -> int {
+    std::vector<const void*> kernels;
+    for (const auto& mb : members)
+      if (std::find(kernels.begin(), kernels.end(), mb.second->kb) == kernels.end())
+        kernels.push_back(mb.second->kb);
+    for (const void* kb : kernels) {
+      std::vector<const Launch*> ls;
+      for (const auto& mb : members)
+        if (mb.second->kb == kb) ls.push_back(mb.second);
+      const size_t asz = launch_arg_bytes(ls[0]->kind);
+      Group g;
+      g.kb = kb; g.n = (int)ls.size(); g.threads = ls[0]->threads; g.lds = 0; g.grid = 0;
+      align(256);
+      g.args_off = off;
+      if (off + asz * ls.size() > st.bytes) return SQR_EHIP;
+      for (size_t k = 0; k < ls.size(); ++k) memcpy(st.host + off + k * asz, &ls[k]->u, asz);
+      off += asz * ls.size();
+      align(16);
+      g.start_off = off;
+      if (off + 4 * (ls.size() + 1) > st.bytes) return SQR_EHIP;
+      int32_t* start = (int32_t*)(st.host + off);
+      int64_t acc = 0;
+      for (size_t k = 0; k < ls.size(); ++k) {
+        start[k] = (int32_t)acc;
+        acc += ls[k]->kind == Launch::kSmall ? 1 : ls[k]->grid;
+        g.lds = std::max(g.lds, ls[k]->lds);
+      }
+      start[ls.size()] = (int32_t)acc;
+      off += 4 * (ls.size() + 1);
+      g.grid = acc;
+      groups.push_back(g);
+    }
+    return SQR_OK;
+  };
+  int rc;
+  for (size_t pos = 0; pos < maxstream; ++pos) {
+    std::vector<std::pair<size_t, const Launch*>> members;
+    for (size_t i = 0; i < who.size(); ++i)
+      if (pos + 2 < plans[i].size()) members.push_back({i, &plans[i][pos]});
+    if ((rc = build(members))) return rc;
+  }
+  for (int tail = 2; tail >= 1; --tail) {   // the reductions, then the small steps
+    std::vector<std::pair<size_t, const Launch*>> members;
+    for (size_t i = 0; i < who.size(); ++i) members.push_back({i, &plans[i][plans[i].size() - tail]});
+    if ((rc = build(members))) return rc;
+  }
+  if (hipMemcpyAsync(st.dev + off0, st.host + off0, off - off0, hipMemcpyHostToDevice, s) != hipSuccess)
+    return SQR_EHIP;
+  for (const Group& g : groups) {
+    BatchTable<char> t;   // the same layout for every argument type
+    t.args = st.dev + g.args_off;
+    t.start = (const int32_t*)(st.dev + g.start_off);
+    t.ncalls = g.n;
+    void* args[] = {&t};
+    if (hipLaunchKernel(g.kb, dim3((unsigned)g.grid), dim3(g.threads), args, g.lds, s) != hipSuccess)
+      return SQR_EHIP;
+  }
+  return SQR_OK;
+}
+
+// Run the calls: every call's initial Gram pass and its first `spec` passes
+// as batched rounds, then, after the device has decided, further rounds for
+// the calls that ask for more passes.
+int run_batch(std::vector<BatchCall>& calls, hipStream_t s, BatchStage& st) {
+  size_t off = 0;
+  int maxspec = 0;
+  for (BatchCall& bc : calls) {
+    const int rc = order_after_previous(bc.b, s);
+    if (rc) return rc;
+    bc.enq = 0;
+    maxspec = std::max(maxspec, bc.spec);
+  }
+  for (int ph = 0; ph <= maxspec; ++ph) {
+    std::vector<int> who, phase;
+    for (size_t i = 0; i < calls.size(); ++i)
+      if (ph == 0 || ph <= calls[i].spec) {
+        who.push_back((int)i);
+        phase.push_back(ph);
+        if (ph > 0) calls[i].enq = ph;
+      }
+    const int rc = enqueue_round(calls, who, phase, st, off, s);
+    if (rc) return rc;
+  }
+  for (;;) {
+    std::vector<int> who, phase;
+    for (size_t i = 0; i < calls.size(); ++i) {
+      BatchCall& bc = calls[i];
+      const int rc = wait_phase(bc.b, s, bc.enq);
+      if (rc) return rc;
+      if (!bc.b->ctrl_host->done && bc.enq < bc.b->opts.max_iter) {
+        who.push_back((int)i);
+        phase.push_back(++bc.enq);
+      }
+    }
+    if (who.empty()) break;
+    const int rc = enqueue_round(calls, who, phase, st, off, s);
+    if (rc) return rc;
+  }
   return SQR_OK;
 }
 
@@ -818,6 +1075,101 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stre
   if (b->ctrl_host->status == SQR_OK) b->n += p;
   if (info) fill_info(b->ctrl_host, info);
   return b->ctrl_host->status;
+}
+
+int sqr_batch(const sqr_opts* opts, sqr_batch_item* items, int32_t count, void* stream) {
+  if (!items || count < 1) return SQR_ENULL;
+  sqr_opts o;
+  sqr_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_ok(o)) return SQR_EOPT;
+  // usage checks of every item, as sqr_orth / sqr_append make them
+  for (int32_t i = 0; i < count; ++i) {
+    sqr_batch_item& it = items[i];
+    it.rc = SQR_OK;
+    memset(&it.info, 0, sizeof(it.info));
+    if (it.kind == SQR_BATCH_ORTH) {
+      const int64_t m = it.m, n = it.cols;
+      if (!it.in || !it.Q || !it.R) it.rc = SQR_ENULL;
+      else if (m < 1 || n < 1 || n > m || it.ld_in < m || it.ldq < m || it.cap < n || it.ldr < it.cap ||
+               it.cap > kMaxSCols || it.ld_in > kMaxLd || it.ldq > kMaxLd)
+        it.rc = SQR_EDIM;
+      else if (o.precision == 1 && n > 16 * kSplitMax)
+        it.rc = SQR_EOPT;
+    } else if (it.kind == SQR_BATCH_APPEND) {
+      sqr_basis* b = it.basis;
+      if (!b || !it.in) it.rc = SQR_ENULL;
+      else if (it.cols < 1 || it.ld_in < b->m || it.ld_in > kMaxLd || b->n + it.cols > b->cap ||
+               b->n + it.cols > b->m)
+        it.rc = SQR_EDIM;
+      for (int32_t k = 0; k < i && it.rc == SQR_OK; ++k)   // one call per handle
+        if (items[k].kind == SQR_BATCH_APPEND && items[k].basis == b) it.rc = SQR_EOPT;
+    } else {
+      it.rc = SQR_EOPT;
+    }
+  }
+  bool any = false;
+  for (int32_t i = 0; i < count; ++i) any = any || items[i].rc == SQR_OK;
+  if (!any) return SQR_OK;   // nothing to run (no HIP call made)
+  set_kernel_attributes();
+  int device = 0;
+  (void)hipGetDevice(&device);
+  std::vector<BatchCall> calls;
+  std::vector<int> idx;
+  size_t need = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    sqr_batch_item& it = items[i];
+    if (it.rc) continue;
+    sqr_basis* b;
+    Call c;
+    int spec;
+    if (it.kind == SQR_BATCH_ORTH) {
+      b = new sqr_basis();
+      b->m = it.m; b->n = it.cols; b->cap = it.cap; b->Q = it.Q; b->ldq = it.ldq; b->R = it.R; b->ldr = it.ldr;
+      b->opts = o;
+      b->device = device;
+      b->noprof = true;
+      const int rc = alloc_workspace(b);
+      if (rc) { sqr_free(b); it.rc = rc; continue; }
+      it.basis = b;
+      c = Call{0, 0, it.cols, it.in, it.ld_in, it.Q, it.ldq};
+      spec = std::min(std::max(o.min_passes, 1), o.max_iter);
+    } else {
+      b = it.basis;
+      if (!b->ws) {
+        const int rc = alloc_workspace(b);
+        if (rc) { it.rc = rc; continue; }
+        b->parked = false;
+      }
+      c = Call{1, b->n, it.cols, it.in, it.ld_in, b->Q + b->n * b->ldq, b->ldq};
+      spec = std::min(2, b->opts.max_iter);
+    }
+    calls.push_back(BatchCall{b, c, 0, spec});
+    idx.push_back(i);
+    // staging bound: every pass of the call, its launches, argument blocks
+    // and start entries, with alignment slack
+    const int64_t P = nblocks(c.p);
+    need += (size_t)(b->opts.max_iter + 1) * (size_t)(P + 4) * (sizeof(Launch) + 8 + 512);
+  }
+  if (calls.empty()) return SQR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  BatchStage st = take_stage(device, need + 4096);
+  int rc = st.host ? run_batch(calls, s, st) : SQR_EHIP;
+  // every queued launch of the batch has read its tables before they are reused
+  if (hipStreamSynchronize(s) != hipSuccess && rc == SQR_OK) rc = SQR_EHIP;
+  put_stage(st);
+  for (size_t k = 0; k < calls.size(); ++k) {
+    sqr_batch_item& it = items[idx[k]];
+    sqr_basis* b = calls[k].b;
+    if (rc) {
+      it.rc = rc;
+      if (it.kind == SQR_BATCH_ORTH) { sqr_free(b); it.basis = nullptr; }
+      continue;
+    }
+    fill_info(b->ctrl_host, &it.info);
+    if (it.kind == SQR_BATCH_APPEND && b->ctrl_host->status == SQR_OK) b->n += it.cols;
+  }
+  return rc;
 }
 
 int sqr_last_info(sqr_basis* b, sqr_info* info) {

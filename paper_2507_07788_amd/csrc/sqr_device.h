@@ -61,6 +61,24 @@ struct WidePassArgs {
   const int32_t* gram32;
 };
 
+// One launch of reduce_slots: sum nslots partial slots (stride doubles apart)
+// of len doubles each into out, in a fixed order.
+struct ReduceArgs {
+  const double* in; int64_t stride; int64_t len;
+  double* out;
+  const int32_t* done;   // NULL in the initial Gram pass of a call
+  int32_t nslots;
+};
+
+// Argument table of a batched launch: call c owns workgroups start[c] ..
+// start[c+1]-1 of the grid and reads args[c] (device memory).
+template <class T>
+struct BatchTable {
+  const T* args;
+  const int32_t* start;   // ncalls + 1 entries
+  int32_t ncalls;
+};
+
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
   const double* E;       // reduced partial Gramians of the pass, block after block

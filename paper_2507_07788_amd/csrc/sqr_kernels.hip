@@ -70,6 +70,19 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Batched launches: the workgroups of call c are start[c] .. start[c+1]-1 of
+// the grid; each reads its call's argument block from the table.
+template <class T>
+__device__ __forceinline__ int batch_call(const BatchTable<T>& t) {
+  int lo = 0, hi = t.ncalls - 1;   // largest c with start[c] <= blockIdx.x
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t.start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 constexpr int kWaves = 4;             // waves per workgroup of block_pass
 constexpr int kThreads = 64 * kWaves;
 constexpr int kYPitch = 17;           // LDS row pitch of a 16x16 tile (doubles)
@@ -94,8 +107,7 @@ constexpr int kTPart = 256;    // doubles per 16x16 tile in LDS
 // variants up to 12 S tiles (their LDS allows three workgroups per CU), one
 // for the wider ones.
 template <int NTW, int WPT, bool APPLY>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
-void block_pass(BlockPassArgs a) {
+__device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const int bid, const int nwg) {
   // LDS: double-buffered partial T tiles (2 x 4 x 256 doubles), then one
   // 16x17 transposition tile per wave; the final cross-group reduction
   // reuses the area.
@@ -108,8 +120,8 @@ void block_pass(BlockPassArgs a) {
   const int x = lane & 15;
   const int g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
-  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;   // row tiles per workgroup
-  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (tiles + nwg - 1) / nwg;   // row tiles per workgroup
+  const int64_t t0 = (int64_t)bid * per;
   const int64_t t1 = min(tiles, t0 + per);
 
   if (a.done && *a.done) {
@@ -321,7 +333,7 @@ void block_pass(BlockPassArgs a) {
 
   // Slot layout: rows 0..ks-1 hold S^T Y, rows ks..ks+15 hold Y^T Y, 16
   // doubles per row.  Tile I row (g + 4r) is S column 16I + g + 4r.
-  double* out = a.part + (int64_t)blockIdx.x * a.part_stride + a.part_off;
+  double* out = a.part + (int64_t)bid * a.part_stride + a.part_off;
   if (G == 1) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
@@ -366,6 +378,19 @@ void block_pass(BlockPassArgs a) {
   }
 }
 
+template <int NTW, int WPT, bool APPLY>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
+void block_pass(BlockPassArgs a) {
+  block_pass_body<NTW, WPT, APPLY>(a, blockIdx.x, gridDim.x);
+}
+template <int NTW, int WPT, bool APPLY>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
+void block_pass_batch(BatchTable<BlockPassArgs> t) {
+  const int c = batch_call(t);
+  block_pass_body<NTW, WPT, APPLY>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+}
+
+
 // Sum the nslots partial slots element-wise.  A workgroup covers kRedElems
 // elements; lane (sub, e) of wave w reads element e of slots
 // 4w + sub + 64k, k = 0, 1, ... (each load instruction takes 128 contiguous
@@ -374,16 +399,17 @@ void block_pass(BlockPassArgs a) {
 // The order of every addition is fixed by nslots alone.
 constexpr int kRedWaves = 16;
 constexpr int kRedElems = 16;
-__global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __restrict__ in,
-                                                             int nslots, int64_t stride,
-                                                             int64_t len,
-                                                             double* __restrict__ out,
-                                                             const int* done) {
+__device__ __forceinline__ void reduce_slots_body(const ReduceArgs& a, const int bid) {
+  const double* __restrict__ in = a.in;
+  const int nslots = a.nslots;
+  const int64_t stride = a.stride, len = a.len;
+  double* __restrict__ out = a.out;
+  const int* done = a.done;
   __shared__ double part[kRedWaves][kRedElems];
   if (done && *done) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int e = lane & (kRedElems - 1), sub = lane >> 4;
-  const int64_t el = (int64_t)blockIdx.x * kRedElems + e;
+  const int64_t el = (int64_t)bid * kRedElems + e;
   double s = 0.0;
   if (el < len) {
 #pragma unroll 4
@@ -400,6 +426,13 @@ __global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(const double* __r
     out[el] = t;
   }
 }
+
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_slots(ReduceArgs a) { reduce_slots_body(a, blockIdx.x); }
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_slots_batch(BatchTable<ReduceArgs> t) {
+  const int c = batch_call(t);
+  reduce_slots_body(t.args[c], blockIdx.x - t.start[c]);
+}
+
 
 // Offset (in doubles) of block J's partial Gramian inside a reduced slot:
 // block J' holds (q16 + 16 J' + 16) rows of 16 doubles, q16 = q rounded up to
@@ -425,14 +458,14 @@ __device__ __forceinline__ int64_t e_off(int q16, int J) {
 constexpr int kNarrowPF = 4;
 
 template <bool APPLY>
-__global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
+__device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const int bid, const int nwg) {
   __shared__ double red[kWaves * 256];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
-  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
-  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (tiles + nwg - 1) / nwg;
+  const int64_t t0 = (int64_t)bid * per;
   const int64_t t1 = min(tiles, t0 + per);
 
   if (a.done && *a.done) {
@@ -524,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wave * 256 + (g + 4 * r) * 16 + x] = accg[r];
   __syncthreads();
-  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+  double* out = a.part + (int64_t)bid * a.part_stride;
   for (int e = threadIdx.x; e < 256; e += kThreads) {
     double t = 0.0;
 #pragma unroll
@@ -532,6 +565,17 @@ __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
     out[e] = t;
   }
 }
+
+template <bool APPLY>
+__global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
+  narrow_pass_body<APPLY>(a, blockIdx.x, gridDim.x);
+}
+template <bool APPLY>
+__global__ __launch_bounds__(kThreads) void narrow_pass_batch(BatchTable<WidePassArgs> t) {
+  const int c = batch_call(t);
+  narrow_pass_body<APPLY>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+}
+
 
 // ---------------------------------------------------------------------------
 // wide_pass: one launch per pass of an orth call whose n columns form NB
@@ -551,7 +595,7 @@ constexpr int kOpSlot = 68;   // one 4 x 16 operand slot, rows padded to 17
 __host__ __device__ constexpr int wide_op_doubles(int nb) { return kWaves * nb * 4 * kOpSlot; }
 
 template <int NB, bool APPLY, bool G32>
-__global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
+__device__ __forceinline__ void wide_pass_body(const WidePassArgs& a, const int bid, const int nwg) {
   extern __shared__ double lds[];
   constexpr int NP = NB * (NB + 1) / 2;           // Gramian blocks (I <= J)
   constexpr int KP = (NP + kWaves - 1) / kWaves;   // blocks per wave
@@ -560,8 +604,8 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
   const int64_t steps = (tiles + kWaves - 1) / kWaves;
-  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
-  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (steps + nwg - 1) / nwg;
+  const int64_t s0 = (int64_t)bid * per;
   const int64_t s1 = min(steps, s0 + per);
 
   if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
@@ -725,7 +769,7 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
   }
 
   // Slot: block J holds rows 0..16J+15 of Gramian columns 16J..16J+15.
-  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+  double* out = a.part + (int64_t)bid * a.part_stride;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (pidx_ok[k]) {
@@ -739,6 +783,17 @@ __global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
     }
   }
 }
+
+template <int NB, bool APPLY, bool G32>
+__global__ __launch_bounds__(kThreads) void wide_pass(WidePassArgs a) {
+  wide_pass_body<NB, APPLY, G32>(a, blockIdx.x, gridDim.x);
+}
+template <int NB, bool APPLY, bool G32>
+__global__ __launch_bounds__(kThreads) void wide_pass_batch(BatchTable<WidePassArgs> t) {
+  const int c = batch_call(t);
+  wide_pass_body<NB, APPLY, G32>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+}
+
 
 // ---------------------------------------------------------------------------
 // Orth calls of 8..16 blocks (113..256 columns): the apply and the Gramian
@@ -780,7 +835,7 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 template <int NB>
-__global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
+__device__ __forceinline__ void wide_apply_body(const WidePassArgs& a, const int bid, const int nwg) {
   extern __shared__ double lds[];
   constexpr int R = apply_resident(NB);           // resident panels
   constexpr int NPF = NB <= 10 ? NB : 8;          // blocks of the next tile prefetched
@@ -789,8 +844,8 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
   const int64_t steps = (tiles + kWaves - 1) / kWaves;
-  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
-  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (steps + nwg - 1) / nwg;
+  const int64_t s0 = (int64_t)bid * per;
   const int64_t s1 = min(steps, s0 + per);
 
   if (a.done && *a.done) {
@@ -912,8 +967,19 @@ __global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
   }
 }
 
+template <int NB>
+__global__ __launch_bounds__(kThreads) void wide_apply(WidePassArgs a) {
+  wide_apply_body<NB>(a, blockIdx.x, gridDim.x);
+}
+template <int NB>
+__global__ __launch_bounds__(kThreads) void wide_apply_batch(BatchTable<WidePassArgs> t) {
+  const int c = batch_call(t);
+  wide_apply_body<NB>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+}
+
+
 template <int NB, bool G32>
-__global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
+__device__ __forceinline__ void gram_pass_body(const WidePassArgs& a, const int bid, const int nwg) {
   extern __shared__ double lds[];
   using Op = typename std::conditional<G32, float, double>::type;
   using Acc = typename std::conditional<G32, f4, d4>::type;
@@ -926,8 +992,8 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
   const int64_t steps = (tiles + kWaves - 1) / kWaves;
-  const int64_t per = (steps + gridDim.x - 1) / gridDim.x;
-  const int64_t s0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (steps + nwg - 1) / nwg;
+  const int64_t s0 = (int64_t)bid * per;
   const int64_t s1 = min(steps, s0 + per);
   if (a.done && *a.done) return;
   if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
@@ -1007,7 +1073,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
   }
   // Slot: block J holds rows 0..16J+15 of Gramian columns 16J..16J+15 (the
   // two MFMA forms place the 16x16 result differently across lanes).
-  double* out = a.part + (int64_t)blockIdx.x * a.part_stride;
+  double* out = a.part + (int64_t)bid * a.part_stride;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (pok[k]) {
@@ -1021,6 +1087,17 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
     }
   }
 }
+
+template <int NB, bool G32>
+__global__ __launch_bounds__(kGramThreads) void gram_pass(WidePassArgs a) {
+  gram_pass_body<NB, G32>(a, blockIdx.x, gridDim.x);
+}
+template <int NB, bool G32>
+__global__ __launch_bounds__(kGramThreads) void gram_pass_batch(BatchTable<WidePassArgs> t) {
+  const int c = batch_call(t);
+  gram_pass_body<NB, G32>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+}
+
 
 // ---------------------------------------------------------------------------
 // small_step: one workgroup of 256 threads finishes a pass.
@@ -1352,7 +1429,7 @@ __device__ void publish(const SmallArgs& a, const Outcome& o) {
                      __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
+__device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   extern __shared__ double lds[];
   __shared__ double red[kSmallWaves];
   // power-iteration vectors, Schur partial sums, then (up to 8 blocks) the
@@ -1923,5 +2000,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) {
     publish(a, Outcome{0, 0, 0, pass, prev_att + attempts, pass - 1, sigma, err});
   }
 }
+
+__global__ __launch_bounds__(kSmallThreads) void small_step(SmallArgs a) { small_step_body(a); }
+// One workgroup per call of the batch.
+__global__ __launch_bounds__(kSmallThreads) void small_step_batch(BatchTable<SmallArgs> t) {
+  small_step_body(t.args[blockIdx.x]);
+}
+
 
 }  // namespace sqr

@@ -10,6 +10,9 @@ Scheduling (continuous, not a queue drained in order):
     has arrived, whose input is ready, whose session has no request in flight
     (a session's requests run in arrival order) and whose new memory fits the
     HBM budget;
+  * with batch = B, a worker takes up to B such requests at once and runs them
+    as one sqr_batch call: the passes of all of them advance together and each
+    kernel launch covers every request of the batch (uneven m, n and p);
   * a request that arrives while others run is admitted as soon as a worker and
     memory are free, and its kernels then run on the device concurrently with
     the kernels of the requests already in flight;
@@ -37,7 +40,7 @@ import time
 import numpy as np
 import torch
 
-from . import Basis, colmajor, sqr_append, sqr_default_opts, sqr_free, sqr_orth, sqr_park
+from . import Basis, colmajor, sqr_append, sqr_batch, sqr_default_opts, sqr_free, sqr_orth, sqr_park
 
 
 @dataclasses.dataclass
@@ -200,13 +203,16 @@ class _Session:
 
 class Server:
     """Runs a list of requests with `workers` concurrent streams under an HBM
-    budget; returns one Result per request.  `keep` maps a session id to a
+    budget; returns one Result per request.  `batch` > 0 runs up to that many
+    requests per library call (sqr_batch).  `keep` maps a session id to a
     callback that receives (Q, R) on the host after the session's last request
     (used by tests)."""
 
     def __init__(self, workers: int = 4, budget_bytes: float | None = None,
-                 lookahead_bytes: float = 8e9, opts=None, keep=None, progress: int = 0):
+                 lookahead_bytes: float = 8e9, opts=None, keep=None, progress: int = 0,
+                 batch: int = 0):
         self.workers = workers
+        self.batch = batch         # 0: one library call per request; B: up to B per sqr_batch
         self.progress = progress   # print a line to stderr every `progress` results
         if budget_bytes is None:
             _, total = torch.cuda.mem_get_info()
@@ -268,6 +274,16 @@ class Server:
         heads.sort()
         return [s for _, s in heads]
 
+    def _take(self, now):
+        """Up to `batch` admissible requests (one per session), oldest first."""
+        got = []
+        while len(got) < max(1, self.batch):
+            g = self._pick(now)
+            if not g:
+                break
+            got.append(g)
+        return got
+
     def _work(self):
         stream = torch.cuda.Stream()
         while True:
@@ -276,56 +292,78 @@ class Server:
                     if self.stop or self.remaining == 0:
                         return
                     now = time.perf_counter() - self.t0
-                    got = self._pick(now)
+                    got = self._take(now)
                     if got:
                         break
                     self.cv.wait(0.0005)
-                r, grow = got
-                X, ready = self.inputs.pop(r.rid)
+                work = [(r, grow) + self.inputs.pop(r.rid) for r, grow in got]
             start = time.perf_counter() - self.t0
-            sess = self.sessions[r.session]
+            outs = []   # (request, info, q) per request
             with torch.cuda.stream(stream):
-                if r.kind == "orth":
-                    if sess.basis is not None:
-                        sqr_free(sess.basis)
-                        sess.basis = None
-                    Q = colmajor(r.m, r.cap)
-                    R = colmajor(r.cap, r.cap)
-                    b, info = sqr_orth(X, cap=r.cap, opts=self.opts, Q=Q, R=R, stream=stream)
-                    sess.basis = b
-                    q = 0
+                calls, qs = [], []
+                for r, grow, X, ready in work:
+                    sess = self.sessions[r.session]
+                    if r.kind == "orth":
+                        if sess.basis is not None:
+                            sqr_free(sess.basis)
+                            sess.basis = None
+                        Q = colmajor(r.m, r.cap)
+                        R = colmajor(r.cap, r.cap)
+                        calls.append(("orth", X, r.cap, Q, R))
+                        qs.append(0)
+                    else:
+                        calls.append(("append", sess.basis, X))
+                        qs.append(sess.basis.n)
+                if self.batch:
+                    # one batched call: the passes of all requests advance
+                    # together, each launch covering every request
+                    res = sqr_batch(calls, opts=self.opts, stream=stream)
+                    for (r, grow, X, ready), call, q, d in zip(work, calls, qs, res):
+                        if d["rc"] < 0:
+                            raise RuntimeError(f"request {r.rid}: sqr_batch item failed with code {d['rc']}")
+                        if r.kind == "orth":
+                            self.sessions[r.session].basis = d["basis"]
+                        outs.append((r, d["info"], q))
                 else:
-                    b = sess.basis
-                    q = b.n
-                    info = sqr_append(b, X, stream=stream)
-                sqr_park(sess.basis)          # waits for the stream; frees scratch
+                    for (r, grow, X, ready), call, q in zip(work, calls, qs):
+                        if r.kind == "orth":
+                            _, A, cap, Q, R = call
+                            b, info = sqr_orth(A, cap=cap, opts=self.opts, Q=Q, R=R, stream=stream)
+                            self.sessions[r.session].basis = b
+                        else:
+                            info = sqr_append(call[1], call[2], stream=stream)
+                        outs.append((r, info, q))
+                for r, _, _ in outs:
+                    sqr_park(self.sessions[r.session].basis)   # waits for the stream; frees scratch
             end = time.perf_counter() - self.t0
-            res = Result(r.rid, r.session, r.kind, info["status"], info["passes"],
-                         r.arrival, ready, start, end,
-                         request_bytes(r.kind, r.m, q, r.cols, info["passes"]))
             with self.cv:
-                if r.kind == "orth":
-                    sess.bytes = 8 * (r.m * r.cap + r.cap * r.cap)
-                self.inflight_inputs -= 8.0 * r.m * r.cols
-                del X
-                self.results.append(res)
-                self.remaining -= 1
-                if self.progress and len(self.results) % self.progress == 0:
-                    print(f"served {len(self.results)} requests, {end:.1f} s",
-                          file=sys.stderr, flush=True)
-                last = not sess.queue
-                if last:
-                    if r.session in self.keep and sess.basis is not None:
-                        bb = sess.basis
-                        self.keep[r.session](bb.q().cpu(), bb.r().cpu())
-                    if sess.basis is not None:
-                        sqr_free(sess.basis)
-                    sess.basis = None
-                    self.resident -= sess.bytes
-                    sess.bytes = 0
-                    self.active.discard(r.session)
-                sess.busy = False
-                self.in_flight -= 1
+                for (r, info, q), (_, grow, X, ready) in zip(outs, work):
+                    sess = self.sessions[r.session]
+                    res = Result(r.rid, r.session, r.kind, info["status"], info["passes"],
+                                 r.arrival, ready, start, end,
+                                 request_bytes(r.kind, r.m, q, r.cols, info["passes"]))
+                    if r.kind == "orth":
+                        sess.bytes = 8 * (r.m * r.cap + r.cap * r.cap)
+                    self.inflight_inputs -= 8.0 * r.m * r.cols
+                    self.results.append(res)
+                    self.remaining -= 1
+                    if self.progress and len(self.results) % self.progress == 0:
+                        print(f"served {len(self.results)} requests, {end:.1f} s",
+                              file=sys.stderr, flush=True)
+                    last = not sess.queue
+                    if last:
+                        if r.session in self.keep and sess.basis is not None:
+                            bb = sess.basis
+                            self.keep[r.session](bb.q().cpu(), bb.r().cpu())
+                        if sess.basis is not None:
+                            sqr_free(sess.basis)
+                        sess.basis = None
+                        self.resident -= sess.bytes
+                        sess.bytes = 0
+                        self.active.discard(r.session)
+                    sess.busy = False
+                    self.in_flight -= 1
+                del work, outs
                 self.cv.notify_all()
 
     def run(self, reqs, seeds=None):

@@ -150,3 +150,21 @@ def test_leading_dimension_limit(sq):
     assert _orth(sq, 100, 10, big, 100, 10, 10) == sq.SQR_EDIM
     assert _orth(sq, 100, 10, 100, big, 10, 10) == sq.SQR_EDIM
     assert _noalloc(sq, 100, 10, big, 100, 10) == sq.SQR_EDIM
+
+
+def test_batch_usage_errors_before_any_gpu_work(sq):
+    """sqr_batch rejects a missing item list and gives every bad item its own
+    usage code (the checks of sqr_orth / sqr_append) without touching a GPU
+    when no item is left to run."""
+    assert sq.lib.sqr_batch(None, None, 1, None) == sq.SQR_ENULL
+    items = (sq.SqrBatchItem * 3)()
+    assert sq.lib.sqr_batch(None, items, 0, None) == sq.SQR_ENULL
+    items[0].kind = sq.SQR_BATCH_ORTH                 # null pointers
+    items[1].kind = sq.SQR_BATCH_ORTH                 # n > m
+    items[1].inp = items[1].Q = items[1].R = 0x1000
+    items[1].m, items[1].cols, items[1].ld_in, items[1].ldq, items[1].cap, items[1].ldr = 10, 11, 10, 10, 11, 11
+    items[2].kind = 7                                 # unknown kind
+    assert sq.lib.sqr_batch(None, items, 3, None) == sq.SQR_OK
+    assert [it.rc for it in items] == [sq.SQR_ENULL, sq.SQR_EDIM, sq.SQR_EOPT]
+    bad = sq.sqr_default_opts(max_iter=0)
+    assert sq.lib.sqr_batch(ctypes.byref(bad), items, 3, None) == sq.SQR_EOPT

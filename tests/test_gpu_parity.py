@@ -449,6 +449,111 @@ def test_serving_mix_matches_each_session_alone():
 
 
 # --------------------------------------------------------------------------
+# batched calls (sqr_batch): the same results as the calls made alone
+# --------------------------------------------------------------------------
+def _alone_and_batched(specs, opts=None):
+    """specs: ("orth", m, n, kappa, cap) or ("append", index of an orth spec,
+    p, kappa).  Every orth runs alone (sqr_orth) and in one batch; then every
+    append runs alone (sqr_append) on the alone bases and in a second batch on
+    the batched bases.  Returns the pairs of (Q, R, info)."""
+    g = np.random.default_rng(31)
+    A, W = {}, {}
+    for i, sp in enumerate(specs):
+        if sp[0] == "orth":
+            A[i] = dev(S.test_matrix(sp[1], sp[2], sp[3], seed=(32, i)))
+        else:
+            m = specs[sp[1]][1]
+            W[i] = dev(S.test_matrix(m, sp[2], sp[3], seed=(33, i)))
+    alone, batched = {}, {}
+    calls, orth_ids = [], []
+    for i, sp in enumerate(specs):
+        if sp[0] != "orth":
+            continue
+        b, info = sq.sqr_orth(A[i], cap=sp[4], opts=opts)
+        alone[i] = (b, info)
+        calls.append(("orth", A[i], sp[4], sq.colmajor(sp[1], sp[4]), sq.colmajor(sp[4], sp[4])))
+        orth_ids.append(i)
+    res = sq.sqr_batch(calls, opts=opts)
+    for i, d in zip(orth_ids, res):
+        assert d["rc"] == 0, (i, d)
+        batched[i] = (d["basis"], d["info"])
+    calls, app_ids = [], []
+    for i, sp in enumerate(specs):
+        if sp[0] != "append":
+            continue
+        alone[i] = (alone[sp[1]][0], sq.sqr_append(alone[sp[1]][0], W[i]))
+        calls.append(("append", batched[sp[1]][0], W[i]))
+        app_ids.append(i)
+    if calls:
+        res = sq.sqr_batch(calls)
+        for i, d in zip(app_ids, res):
+            assert d["rc"] == 0, (i, d)
+            batched[i] = (batched[specs[i][1]][0], d["info"])
+    return alone, batched
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_calls_alone(precision):
+    """Orthogonalisations of uneven m and n (one block, whole-pass, split and
+    per-block routes) and appends of uneven p, batched, give the results of
+    the same calls made alone, bit for bit, and the oracle's accuracy."""
+    specs = [("orth", 3001, 7, 1e6, 20), ("orth", 20011, 20, 1e10, 36), ("orth", 9000, 40, 1e3, 56),
+             ("orth", 5003, 130, 1e8, 130), ("orth", 4001, 230, 1e4, 230)]
+    if precision == 0:
+        specs.append(("orth", 2500, 300, 1e12, 300))
+    specs += [("append", 0, 13, 1e4), ("append", 1, 16, 1e8), ("append", 2, 3, 1e2)]
+    opts = sq.sqr_default_opts(precision=precision)
+    alone, batched = _alone_and_batched(specs, opts)
+    for i, sp in enumerate(specs):
+        (ba, ia), (bb, ib) = alone[i], batched[i]
+        assert ia["status"] == ib["status"] == 0, (i, ia, ib)
+        assert ia["passes"] == ib["passes"] and ia["sigma"] == ib["sigma"], i
+        assert torch.equal(ba.q(), bb.q()) and torch.equal(ba.r(), bb.r()), i
+    for i, sp in enumerate(specs):
+        if sp[0] == "orth":
+            assert O.loo(host(batched[i][0].q())) <= 1e-12
+
+
+def test_batch_item_errors_leave_the_others_running():
+    """A bad item (a second append to the same basis, an append past the
+    capacity) gets its usage code; the other items of the batch complete."""
+    A = dev(S.test_matrix(5000, 12, 1e4, seed=(34,)))
+    b, _ = sq.sqr_orth(A, cap=20)
+    W1 = dev(S.test_matrix(5000, 4, 1e2, seed=(35,)))
+    W2 = dev(S.test_matrix(5000, 9, 1e2, seed=(36,)))
+    res = sq.sqr_batch([("append", b, W1), ("append", b, W1),
+                        ("orth", A, 12, sq.colmajor(5000, 12), sq.colmajor(12, 12))])
+    assert [d["rc"] for d in res] == [0, sq.SQR_EOPT, 0]
+    assert res[0]["info"]["status"] == 0 and b.n == 16
+    res = sq.sqr_batch([("append", b, W2)])
+    assert res[0]["rc"] == sq.SQR_EDIM and b.n == 16
+
+
+def test_serving_batched_mix_matches_each_session_alone():
+    """Serving with batched launches (up to eight requests per sqr_batch, two
+    streams): every session's final basis equals the basis of its requests
+    run alone, one call at a time on one stream, to the bit."""
+    from paper_2507_07788_amd import serve
+    reqs = serve.synthetic_workload(64, 8, seed=23, m_range=(3000, 40000),
+                                    n_range=(8, 40), p_range=(1, 16))
+    serve.poisson_arrivals(reqs, 1e5, seed=24)
+    mixed = {}
+    keep = {s: (lambda s: lambda Q, R: mixed.__setitem__(s, (Q, R)))(s) for s in range(8)}
+    res = serve.Server(workers=2, batch=8, keep=keep).run(reqs)
+    assert len(res) == 64 and all(r.status == 0 for r in res)
+    # some requests shared a batch (the same start and end)
+    assert any(a.start == b.start and a.end == b.end for a in res for b in res if a.rid != b.rid)
+    for s in range(8):
+        alone = {}
+        mine = [serve.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs if r.session == s]
+        serve.Server(workers=1, keep={s: lambda Q, R: alone.__setitem__(0, (Q, R))}).run(
+            mine, seeds={r.rid: 1_000_003 * (r.rid + 1) for r in mine})
+        Qm, Rm = mixed[s]
+        Qa, Ra = alone[0]
+        assert torch.equal(Qm, Qa) and torch.equal(Rm, Ra), s
+
+
+# --------------------------------------------------------------------------
 # full sizes of the measured configurations (m = 4e6 and 2e7 rows)
 # --------------------------------------------------------------------------
 def _invariants_dev(A, Q, R, n):
