@@ -371,8 +371,9 @@ def orth_gpu(m, n, kappa, precision, steps, warmup, seed=(3,), A=None):
     return res
 
 
-def serve_gpu(requests, sessions, workers, rate):
-    """Serving run: returns (summary dict, saturated summary, rate, requests)."""
+def serve_gpu(requests, sessions, workers, rate, batch=0):
+    """Serving run: returns (summary dict, saturated summary, rate, requests).
+    batch > 0: up to that many requests per batched library call."""
     import torch
     from paper_2507_07788_amd import serve
 
@@ -380,12 +381,12 @@ def serve_gpu(requests, sessions, workers, rate):
     # saturated rate: a calibration batch of whole sessions, all arriving at once
     cal_sessions = set(range(min(16, sessions)))
     cal = [serve.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs if r.session in cal_sessions]
-    cres = serve.Server(workers=workers, progress=500).run(cal)
+    cres = serve.Server(workers=workers, batch=batch, progress=500).run(cal)
     csum = serve.summarize(cres)
     rate = rate if rate > 0 else 0.8 * csum["req_per_s"]
     serve.poisson_arrivals(reqs, rate)
     torch.cuda.synchronize()
-    res = serve.Server(workers=workers, progress=1000).run(reqs)
+    res = serve.Server(workers=workers, batch=batch, progress=1000).run(reqs)
     summ = serve.summarize(res)
     return summ, csum, rate, reqs
 
@@ -478,14 +479,20 @@ def main_growth(args):
             mix = subs[f"C3_orth_4e6x{n}_k1e4_mixed"]
             mix["speedup_vs_fp64"] = round(f64["ms"] / mix["ms"], 3)
             del A
-        summ, csum, rate, reqs = serve_gpu(args.sub_requests, args.sub_sessions, args.workers, 0.0)
-        subs["C4_serve"] = {"requests": args.sub_requests, "sessions": args.sub_sessions,
-                            "workers": args.workers, "rate_per_s": round(rate, 2),
-                            "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
-                            "mean_ms": summ["mean_ms"], "req_per_s": summ["req_per_s"],
-                            "GBs": summ["GBs"], "ok": summ["ok"], "saturated": csum,
-                            "latency": "from arrival to the end of the request's stream work"}
-        log(f"sub C4: p50 {summ['p50_ms']} ms, p99 {summ['p99_ms']} ms")
+        # both modes at the same offered load: 0.8 x the batched mode's
+        # saturated rate, measured on a calibration batch of whole sessions
+        rate = 0.0
+        for key, workers, batch in (("C4_serve", args.batch_workers, args.batch),
+                                    ("C4_serve_unbatched", args.workers, 0)):
+            summ, csum, rate, reqs = serve_gpu(args.sub_requests, args.sub_sessions, workers, rate, batch)
+            subs[key] = {"requests": args.sub_requests, "sessions": args.sub_sessions,
+                         "workers": workers, "batch": batch, "rate_per_s": round(rate, 2),
+                         "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
+                         "mean_ms": summ["mean_ms"], "req_per_s": summ["req_per_s"],
+                         "GBs": summ["GBs"], "ok": summ["ok"], "late_inputs": summ["late_inputs"],
+                         "saturated": csum,
+                         "latency": "from arrival to the end of the request's stream work"}
+            log(f"sub {key}: p50 {summ['p50_ms']} ms, p99 {summ['p99_ms']} ms")
     if not args.no_cpu_baseline:
         with pinned_host() as host:
             v, t = cpu_growth(A0, Ws, args.m, 10, 10, reps=3)
@@ -536,16 +543,18 @@ def main_orth(args):
 
 
 def main_serve(args):
-    summ, csum, rate, reqs = serve_gpu(args.requests, args.sessions, args.workers, args.rate)
+    workers = args.batch_workers if args.batch else args.workers
+    summ, csum, rate, reqs = serve_gpu(args.requests, args.sessions, workers, args.rate, args.batch)
     out = {
         "metric": METRIC, "value": summ["GBs"], "unit": "GB/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": round(summ["makespan_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"serving: {args.requests} requests from {args.sessions} sessions, "
-                               f"Poisson arrivals at {rate:.1f}/s, {args.workers} streams",
+                               f"Poisson arrivals at {rate:.1f}/s, {workers} streams, "
+                               f"batches of up to {args.batch}",
                    "requests": args.requests, "sessions": args.sessions,
-                   "workers": args.workers, "rate_per_s": round(rate, 2)},
+                   "workers": workers, "batch": args.batch, "rate_per_s": round(rate, 2)},
         "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
         "req_per_s": summ["req_per_s"], "ok": summ["ok"], "saturated": csum,
         "roofline": None, "cpu_baseline": None,
@@ -602,7 +611,10 @@ def main():
     ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
     ap.add_argument("--sub-requests", type=int, default=2000, help="growth: serving sub-run requests")
     ap.add_argument("--sub-sessions", type=int, default=64, help="growth: serving sub-run sessions")
-    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent streams")
+    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent streams (unbatched)")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="serve: requests per batched library call (0: one call per request)")
+    ap.add_argument("--batch-workers", type=int, default=2, help="serve: concurrent streams (batched)")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serve: arrivals per second (0: 0.8 x the measured saturated rate)")
     args = ap.parse_args()
