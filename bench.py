@@ -374,8 +374,12 @@ def orth_gpu(m, n, kappa, precision, steps, warmup, seed=(3,), A=None):
 def serve_gpu(requests, sessions, workers, rate, batch=0):
     """Serving run: returns (summary dict, saturated summary, rate, requests).
     batch > 0: up to that many requests per batched library call."""
+    import gc
     import torch
     from paper_2507_07788_amd import serve
+
+    gc.collect()
+    torch.cuda.empty_cache()   # earlier runs' idle blocks back to the device
 
     reqs = serve.synthetic_workload(requests, sessions)
     # saturated rate: a calibration batch of whole sessions, all arriving at once
@@ -383,6 +387,9 @@ def serve_gpu(requests, sessions, workers, rate, batch=0):
     cal = [serve.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs if r.session in cal_sessions]
     cres = serve.Server(workers=workers, batch=batch, progress=500).run(cal)
     csum = serve.summarize(cres)
+    del cres
+    gc.collect()
+    torch.cuda.empty_cache()
     rate = rate if rate > 0 else 0.8 * csum["req_per_s"]
     serve.poisson_arrivals(reqs, rate)
     torch.cuda.synchronize()

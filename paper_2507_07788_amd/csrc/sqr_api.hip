@@ -157,6 +157,8 @@ struct sqr_basis {
   Ctrl last{};                       // outcome of the last call (kept while parked)
   bool parked = false;               // workspace returned to the pool
   bool noprof = false;               // never recorded by the profiling hooks
+  int publish_from = 0;              // first phase the host waits for (small_step
+                                     // publishes its state from there on, and at the end)
   Ctrl* ctrl_host = nullptr;         // pinned, written by small_step
   Ctrl* ctrl_host_dev = nullptr;     // its device address
   double *part = nullptr, *stage = nullptr;
@@ -629,7 +631,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     k.R = b->R; k.ldr = b->ldr;
     k.X = b->X;
     k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
-    k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256;
+    k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256; k.publish_from = b->publish_from;
     k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
     k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
     k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
@@ -740,11 +742,12 @@ int order_after_previous(sqr_basis* b, hipStream_t s) {
 int run_call(sqr_basis* b, const Call& c, hipStream_t s, bool sync, int spec) {
   int rc = order_after_previous(b, s);
   if (rc) return rc;
+  const int maxit = b->opts.max_iter;
+  const int first = sync ? std::min(spec, maxit) : maxit;
+  b->publish_from = sync ? first : maxit + 1;   // async: only the end is published
   rc = launch_gram(b, c, 0, s);
   if (rc) return rc;
-  const int maxit = b->opts.max_iter;
   int enq = 0;
-  const int first = sync ? std::min(spec, maxit) : maxit;
   for (; enq < first; ++enq)
     if ((rc = launch_gram(b, c, enq + 1, s))) return rc;
   if (!sync) return SQR_OK;
@@ -899,6 +902,7 @@ int run_batch(std::vector<BatchCall>& calls, hipStream_t s, BatchStage& st) {
     const int rc = order_after_previous(bc.b, s);
     if (rc) return rc;
     bc.enq = 0;
+    bc.b->publish_from = bc.spec;
     maxspec = std::max(maxspec, bc.spec);
   }
   for (int ph = 0; ph <= maxspec; ++ph) {

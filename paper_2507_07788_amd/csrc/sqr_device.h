@@ -99,6 +99,7 @@ struct SmallArgs {
   Ctrl* ctrl;
   Ctrl* hctrl;           // pinned host mirror (device address), or NULL
   int64_t stamp_base;    // call id * 256
+  int32_t publish_from;  // first phase whose state the host waits for
   // options
   int32_t first_pass_shift, min_passes, max_iter, max_escalations, power_steps;
   int32_t shift_policy;  // orth: 0 recompute (Algorithm 1), 1 none, 2 fixed

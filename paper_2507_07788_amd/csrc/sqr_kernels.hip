@@ -1402,28 +1402,18 @@ __host__ __device__ inline int64_t small_arena(int q, int p) {
   return 3 * pp + qp + (qp > pp ? qp : pp);
 }
 
-// Write this small_step's outcome to the pinned host mirror, then its stamp
-// (call id and phase), so a host that sees the stamp also sees the state.
-// Fields not passed keep the values earlier phases of the call wrote; phase 0
-// starts from a cleared mirror.  Thread 0 only.
-struct Outcome {
-  int done, status, converged;
-  int passes, attempts;     // < 0: unchanged
-  int sigma_idx;            // < 0: unchanged
-  double sigma, orth_fro;
-};
-__device__ void publish(const SmallArgs& a, const Outcome& o) {
+// Copy the call's device state (which thread 0 has just brought up to date)
+// to the pinned host mirror, then the stamp (call id and phase), so a host
+// that sees the stamp also sees the state.  Only the phases the host waits
+// for publish (from a.publish_from on) and the phase that ends the call; the
+// mirror always receives the whole state.  Thread 0 only.
+__device__ void publish(const SmallArgs& a, const Ctrl* c) {
   Ctrl* h = a.hctrl;
-  if (!h) return;
-  if (a.phase == 0) {
-    h->passes = 0; h->chol_attempts = 0;
-    for (int i = 0; i < 16; ++i) h->sigma[i] = 0.0;
-  }
-  h->done = o.done; h->status = o.status; h->converged = o.converged;
-  if (o.passes >= 0) h->passes = o.passes;
-  if (o.attempts >= 0) h->chol_attempts = o.attempts;
-  if (o.sigma_idx >= 0 && o.sigma_idx < 16) h->sigma[o.sigma_idx] = o.sigma;
-  h->orth_fro = o.orth_fro;
+  if (!h || (!c->done && a.phase < a.publish_from)) return;
+  h->done = c->done; h->status = c->status; h->converged = c->converged;
+  h->passes = c->passes; h->chol_attempts = c->chol_attempts;
+  for (int i = 0; i < 16; ++i) h->sigma[i] = c->sigma[i];
+  h->orth_fro = c->orth_fro;
   __threadfence_system();
   __hip_atomic_store(&h->stamp, a.stamp_base + a.phase, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1809,7 +1799,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
       c->converged = (status == 0);
       c->orth_fro = err;
       c->done = 1;
-      publish(a, Outcome{1, status, status == 0, -1, -1, -1, 0.0, err});
+      publish(a, c);
     }
     return;
   }
@@ -1862,7 +1852,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
       c->chol_attempts = prev_att + attempts;
       c->orth_fro = err;
       c->done = 1;
-      publish(a, Outcome{1, 2, 0, -1, prev_att + attempts, -1, 0.0, err});
+      publish(a, c);
     }
     return;
   }
@@ -1997,7 +1987,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     if (pass <= 16) c->sigma[pass - 1] = sigma;
     c->chol_attempts = prev_att + attempts;
     c->orth_fro = err;
-    publish(a, Outcome{0, 0, 0, pass, prev_att + attempts, pass - 1, sigma, err});
+    publish(a, c);
   }
 }
 

@@ -215,8 +215,14 @@ class Server:
         self.batch = batch         # 0: one library call per request; B: up to B per sqr_batch
         self.progress = progress   # print a line to stderr every `progress` results
         if budget_bytes is None:
-            _, total = torch.cuda.mem_get_info()
-            budget_bytes = 0.85 * total - 8e9
+            # resident bases may take 80 % of the memory that is free now (the
+            # caching allocator's idle blocks returned first), less a reserve
+            # for inputs in flight, the library's workspaces and the runtime's
+            # scratch: a dispatch whose scratch cannot be allocated aborts the
+            # queue (HSA_STATUS_ERROR_OUT_OF_RESOURCES)
+            torch.cuda.empty_cache()
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = 0.8 * free - lookahead_bytes - 8e9
         self.budget = budget_bytes
         self.lookahead = lookahead_bytes
         self.opts = opts if opts is not None else sqr_default_opts()
