@@ -185,6 +185,27 @@ int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,
                void* stream, sqr_info* info);
 
+/*
+ * sqr_panel -- Algorithm 3 (pnCholQR, the panel scheme of Sec. 2.3): split A
+ * (m x n) into r panels of nearly equal width, columns [e_i, e_{i+1}) with
+ * e_i = i n / r rounded to the nearest integer (ties to even), and apply
+ * Algorithm 2 to each in turn, starting from an empty basis (the first panel
+ * is Algorithm 2 with q = 0: its first shift is the 2u floor).
+ *
+ *   out, opts, A, lda, Q, ldq, cap, R, ldr, stream: as sqr_orth; A is read
+ *            only, Q[:, 0:n] and R[0:n, 0:n] receive the factors.
+ *   r        number of panels, 1 <= r <= n.
+ *   info     outcome of the last panel's call (required to be waited for:
+ *            every panel waits for the device's decision).
+ * On a non-zero status of panel i the handle keeps the basis of panels
+ * 0..i-1 (sqr_cols tells its width) and the later panels are not run.
+ * Errors: as sqr_orth, and SQR_EDIM for r < 1 or r > n, SQR_EOPT for
+ * precision 1 (the append always runs in FP64).
+ */
+int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const double* A, int64_t lda,
+              int64_t r, double* Q, int64_t ldq, int64_t cap, double* R, int64_t ldr, void* stream,
+              sqr_info* info);
+
 /* Outcome of the handle's last sqr_orth / sqr_append call; synchronises the
  * stream of that call.  Returns the status, or SQR_ENULL. */
 int sqr_last_info(sqr_basis* b, sqr_info* info);

@@ -81,6 +81,9 @@ def _load():
     lib.sqr_orth_noalloc.argtypes = [ctypes.POINTER(SqrOpts), I64, I64, P, I64, P, I64,
                                      P, I64, P, ctypes.POINTER(SqrInfo)]
     lib.sqr_orth_noalloc.restype = I32
+    lib.sqr_panel.argtypes = [ctypes.POINTER(P), ctypes.POINTER(SqrOpts), I64, I64, P, I64, I64,
+                              P, I64, I64, P, I64, P, ctypes.POINTER(SqrInfo)]
+    lib.sqr_panel.restype = I32
     lib.sqr_batch.argtypes = [ctypes.POINTER(SqrOpts), ctypes.POINTER(SqrBatchItem), ctypes.c_int32, P]
     lib.sqr_batch.restype = I32
     lib.sqr_append.argtypes = [P, P, I64, I64, P, ctypes.POINTER(SqrInfo)]
@@ -190,6 +193,32 @@ def sqr_orth(A: torch.Tensor, cap: int | None = None, opts: SqrOpts | None = Non
     if rc < 0:
         raise RuntimeError(f"sqr_orth failed with code {rc}")
     return Basis(h, Q, R, m, cap), (info.as_dict() if sync else None)
+
+
+def sqr_panel(A: torch.Tensor, r: int, cap: int | None = None, opts: SqrOpts | None = None,
+              Q: torch.Tensor | None = None, R: torch.Tensor | None = None, stream=None):
+    """Algorithm 3 (the panel scheme): r panels of A appended in turn to an
+    empty basis.  Returns (Basis, info of the last panel); raises ValueError
+    on inconsistent shapes or devices and RuntimeError on other usage
+    errors."""
+    if A.dim() != 2:
+        raise ValueError("A must be a matrix")
+    m, n = A.shape
+    cap = n if cap is None else cap
+    if Q is None:
+        Q = colmajor(m, cap, device=A.device)
+    if R is None:
+        R = colmajor(cap, cap, device=A.device)
+    _check_matrix("Q", Q, m, cap, A.device)
+    _check_matrix("R", R, cap, cap, A.device)
+    h = ctypes.c_void_p()
+    info = SqrInfo()
+    rc = lib.sqr_panel(ctypes.byref(h), ctypes.byref(opts) if opts is not None else None,
+                       m, n, A.data_ptr(), _ld(A), r, Q.data_ptr(), _ld(Q), cap,
+                       R.data_ptr(), _ld(R), _stream(stream), ctypes.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"sqr_panel failed with code {rc}")
+    return Basis(h, Q, R, m, cap), info.as_dict()
 
 
 def sqr_orth_noalloc(A: torch.Tensor, Q: torch.Tensor, R: torch.Tensor,

@@ -19,6 +19,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -1174,6 +1175,44 @@ int sqr_batch(const sqr_opts* opts, sqr_batch_item* items, int32_t count, void* 
     if (it.kind == SQR_BATCH_APPEND && b->ctrl_host->status == SQR_OK) b->n += it.cols;
   }
   return rc;
+}
+
+int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const double* A, int64_t lda,
+              int64_t r, double* Q, int64_t ldq, int64_t cap, double* R, int64_t ldr, void* stream,
+              sqr_info* info) {
+  if (!out || !A || !Q || !R) return SQR_ENULL;
+  if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap || r < 1 || r > n)
+    return SQR_EDIM;
+  if (cap > kMaxSCols || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  sqr_opts o;
+  sqr_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_ok(o) || o.precision != 0) return SQR_EOPT;
+  set_kernel_attributes();
+  sqr_basis* b = new sqr_basis();
+  b->m = m; b->n = 0; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
+  b->opts = o;
+  (void)hipGetDevice(&b->device);
+  int rc = alloc_workspace(b);
+  if (rc) { sqr_free(b); return rc; }
+  hipStream_t s = (hipStream_t)stream;
+  // panel i holds columns [e_i, e_{i+1}), e_i = i n / r rounded to the
+  // nearest integer (ties to even), e_r = n
+  int64_t c0 = 0;
+  for (int64_t i = 0; i < r; ++i) {
+    const int64_t c1 = (i + 1 == r) ? n : (int64_t)nearbyint((double)(i + 1) * ((double)n / (double)r));
+    const int64_t p = c1 - c0;
+    if (p < 1) continue;
+    Call c{1, b->n, p, A + c0 * lda, lda, b->Q + b->n * b->ldq, b->ldq};
+    rc = run_call(b, c, s, true, 2);
+    if (rc) { (void)hipStreamSynchronize(s); sqr_free(b); return rc; }
+    if (b->ctrl_host->status != SQR_OK) break;   // the basis keeps the panels done so far
+    b->n += p;
+    c0 = c1;
+  }
+  *out = b;
+  if (info) fill_info(b->ctrl_host, info);
+  return b->ctrl_host->status;
 }
 
 int sqr_last_info(sqr_basis* b, sqr_info* info) {

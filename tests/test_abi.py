@@ -168,3 +168,18 @@ def test_batch_usage_errors_before_any_gpu_work(sq):
     assert [it.rc for it in items] == [sq.SQR_ENULL, sq.SQR_EDIM, sq.SQR_EOPT]
     bad = sq.sqr_default_opts(max_iter=0)
     assert sq.lib.sqr_batch(ctypes.byref(bad), items, 3, None) == sq.SQR_EOPT
+
+
+def test_panel_usage_errors_before_any_gpu_work(sq):
+    """sqr_panel (Algorithm 3) rejects r outside 1..n and the mixed form
+    before any HIP call."""
+    h = ctypes.c_void_p()
+    P = lambda: ctypes.c_void_p(0x1000)   # never dereferenced
+
+    def panel(m, n, r, opts=None):
+        return sq.lib.sqr_panel(ctypes.byref(h), ctypes.byref(opts) if opts else None, m, n, P(), m, r,
+                                P(), m, n, P(), n, None, None)
+    assert panel(100, 10, 0) == sq.SQR_EDIM
+    assert panel(100, 10, 11) == sq.SQR_EDIM
+    assert panel(10, 11, 2) == sq.SQR_EDIM
+    assert panel(100, 10, 2, sq.sqr_default_opts(precision=1)) == sq.SQR_EOPT

@@ -449,6 +449,37 @@ def test_serving_mix_matches_each_session_alone():
 
 
 # --------------------------------------------------------------------------
+# the panel scheme (Algorithm 3) on a given matrix
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("r", [1, 2, 3, 37])
+def test_panel_hadamard_bitwise(r):
+    """sqr_panel on A = H T reaches the closed form R = 2^k T, Q = H / 2^k
+    bit for bit, one pass per panel, as the oracle's panel scheme does."""
+    k, n = 5, 37
+    H = S.hadamard(4 ** k)[:, :n]
+    g = np.random.default_rng(5)
+    T = np.triu(g.integers(-1, 2, size=(n, n)).astype(np.float64), 1) + np.diag(2.0 ** g.integers(0, 3, size=n))
+    b, info = sq.sqr_panel(dev(H @ T), r)
+    assert info["status"] == 0 and info["passes"] == 1 and b.n == n
+    assert np.array_equal(host(b.r()), 2.0 ** k * T)
+    assert np.array_equal(host(b.q()), H / 2.0 ** k)
+
+
+@pytest.mark.parametrize("m,n,r,kappa", [(3000, 20, 2, 1e4), (5000, 64, 4, 1e8), (4097, 130, 3, 1e6),
+                                         (2000, 300, 5, 1e3), (1000, 40, 40, 1e2), (20000, 100, 1, 1e10),
+                                         (6000, 48, 3, 1e15)])
+def test_panel_parity(m, n, r, kappa):
+    """sqr_panel against the oracle's Algorithm 3: the same outcome, R and Q
+    within the tolerances (invariants only at kappa >= 1e12)."""
+    A = S.test_matrix(m, n, kappa, seed=(40, r))
+    Qo, Ro, infos = O.panel(A, r)
+    assert all(i["status"] == O.OK for i in infos)
+    b, info = sq.sqr_panel(dev(A), r)
+    assert info["status"] == 0 and b.n == n
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+# --------------------------------------------------------------------------
 # batched calls (sqr_batch): the same results as the calls made alone
 # --------------------------------------------------------------------------
 def _alone_and_batched(specs, opts=None):

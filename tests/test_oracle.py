@@ -404,6 +404,22 @@ def test_panel_scheme_matches_householder(r):
     assert O.loo(Q) <= 1e-12
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 37])
+def test_panel_scheme_hadamard_closed_form(r):
+    """Algorithm 3 on A = H T (H Hadamard columns, T a small integer upper
+    triangle): every panel's Gram, Schur complement and factor are exact, so
+    R = 2^k T and Q = H / 2^k bit for bit, one pass per panel, whatever r
+    (the first panel is Algorithm 2 on an empty basis)."""
+    k, n = 5, 37
+    H = S.hadamard(4 ** k)[:, :n]
+    g = np.random.default_rng(5)
+    T = np.triu(g.integers(-1, 2, size=(n, n)).astype(np.float64), 1) + np.diag(2.0 ** g.integers(0, 3, size=n))
+    Q, R, infos = O.panel(H @ T, r)
+    assert len(infos) == r and all(i["status"] == O.OK and i["passes"] == 1 for i in infos)
+    assert np.array_equal(R, 2.0 ** k * T)
+    assert np.array_equal(Q, H / 2.0 ** k)
+
+
 def test_panel_scheme_ill_conditioned():
     A = S.test_matrix(2000, 20, 1e15, seed=(25,))
     Q, R, infos = O.panel(A, 4)
