@@ -20,7 +20,8 @@ baseline.  The CPU baselines run last, pinned to the physical cores of NUMA
 node 0 (at most 16 threads, the host share of one GPU), median of repeats.
 
 Other workloads: --workload orth (one orthogonalisation), serve (the full
-serving run), sweep (the m- and n-sweeps of Fig. 3b/3c at kappa 1e20).
+serving run), sweep (the m- and n-sweeps of Fig. 3b/3c at kappa 1e20), panel
+(the panel scheme against Algorithm 1, Fig. 4's shape up to n = 512).
 
 Prints one JSON line (sweep: one line per point, then a summary line).
 --gpus N > 1 is refused: this program runs on one GPU.
@@ -596,6 +597,51 @@ def main_sweep(args):
                       "ok": all(r["ok"] for r in rows)}))
 
 
+PANEL_N = [128, 256, 384, 512]
+
+
+def main_panel(args):
+    """Fig. 4's comparison at m = 1e6, kappa = 1e5: Algorithm 1 as printed
+    (rsCholQR: no first-pass shift, stopping test from the first pass), the
+    CholQR3 start, and the panel scheme with r = 2..5 panels, for n up to 512
+    (the library's width limit).  One JSON line per point, then a summary."""
+    import torch
+    import paper_2507_07788_amd as sq
+    import synth
+    m = 1_000_000
+    rows = []
+    for n in PANEL_N:
+        A = synth.test_matrix_device(m, n, 1e5, (50,))
+        Q, R = sq.colmajor(m, n), sq.colmajor(n, n)
+        variants = [("rsCholQR", None), ("CholQR3", None)] + [(f"pnCholQR({r})", r) for r in range(2, 6)]
+        for name, r in variants:
+            def call():
+                if r is None:
+                    kw = dict(first_pass_shift=0, min_passes=0) if name == "rsCholQR" else {}
+                    return sq.sqr_orth(A, Q=Q, R=R, opts=sq.sqr_default_opts(**kw))
+                return sq.sqr_panel(A, r, Q=Q, R=R)
+            for _ in range(args.warmup):
+                b, info = call()
+                sq.sqr_free(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                b, info = call()
+                sq.sqr_free(b)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            loo, rrr = _orth_invariants(A, Q, R, m, n)
+            row = {"variant": name, "m": m, "n": n, "kappa": 1e5, "ms": round(dt * 1e3, 3),
+                   "status": info["status"], "loo": loo, "rrr": rrr,
+                   "ok": info["status"] == 0 and loo <= 1e-12 and rrr <= 1e-13}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+        del A, Q, R
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "panel scheme vs Algorithm 1 (Fig. 4 shape, m = 1e6, kappa 1e5)",
+                      "points": len(rows), "ok": all(r["ok"] for r in rows)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -607,10 +653,11 @@ def main():
     ap.add_argument("--no-sub", action="store_true", help="growth: skip the sub-runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["growth", "serve", "orth", "sweep"], default="growth",
+    ap.add_argument("--workload", choices=["growth", "serve", "orth", "sweep", "panel"], default="growth",
                     help="growth: the basis-growth step and the sub-runs (default); serve: the "
                          "serving loop; orth: one CholQR3 of an m x n matrix (--m, --n, --kappa, "
-                         "--precision); sweep: the m- and n-sweeps of Fig. 3b/3c")
+                         "--precision); sweep: the m- and n-sweeps of Fig. 3b/3c; panel: the panel "
+                         "scheme against Algorithm 1 (Fig. 4 shape)")
     ap.add_argument("--n", type=int, default=128, help="orth: columns")
     ap.add_argument("--kappa", type=float, default=1e12, help="orth: condition number")
     ap.add_argument("--precision", type=int, default=0, help="orth: 0 FP64, 1 mixed")
@@ -629,7 +676,7 @@ def main():
         print(json.dumps({"error": "this program runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     {"growth": main_growth, "serve": main_serve, "orth": main_orth,
-     "sweep": main_sweep}[args.workload](args)
+     "sweep": main_sweep, "panel": main_panel}[args.workload](args)
 
 
 if __name__ == "__main__":
