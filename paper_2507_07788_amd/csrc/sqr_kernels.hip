@@ -635,11 +635,11 @@ __device__ __forceinline__ void wide_pass_body(const WidePassArgs& a, const int 
   // Input of one tile in D layout: lane (x, g) register r of block J holds
   // W[row x][16 J + g + 4 r]; columns past n read zero (buffer range), rows
   // past m are masked.
+  // (rows past m read a clamped row: the consumers zero those rows, so the
+  // loads are not masked here and stay in flight until their use)
   auto load_w = [&](int64_t tile, d4 (&w)[NB]) {
     const int64_t row = tile * 16 + x;
-    const bool row_ok = row < a.m;
-    const int64_t rowc = row_ok ? row : a.m - 1;
-    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
     for (int J = 0; J < NB; ++J) {
       // one descriptor per 16-column block
@@ -648,9 +648,7 @@ __device__ __forceinline__ void wide_pass_body(const WidePassArgs& a, const int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
-        const uint64_t bits = __builtin_bit_cast(uint64_t,
-            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
-        w[J][r] = __builtin_bit_cast(double, bits & keep);
+        w[J][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
       }
     }
   };
@@ -862,11 +860,11 @@ __device__ __forceinline__ void wide_apply_body(const WidePassArgs& a, const int
 
   // Block J of one tile in D layout (columns past n read zero, rows past m
   // are masked).
+  // (rows past m read a clamped row; their outputs are zeroed and not
+  // stored, so the loads are not masked and stay in flight until their use)
   auto load_block = [&](int64_t tile, int J) -> d4 {
     const int64_t row = tile * 16 + x;
-    const bool row_ok = row < a.m;
-    const int64_t rowc = row_ok ? row : a.m - 1;
-    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
     // one descriptor per 16-column block
     const int64_t nrec = (a.n - 1 >= 16 * J) ? (((int64_t)(a.n - 1 - 16 * J) * a.ldw + a.m) * 8) : 0;
     const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win + (int64_t)(16 * J) * a.ldw, nrec);
@@ -874,9 +872,7 @@ __device__ __forceinline__ void wide_apply_body(const WidePassArgs& a, const int
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
-      const uint64_t bits = __builtin_bit_cast(uint64_t,
-          __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
-      w[r] = __builtin_bit_cast(double, bits & keep);
+      w[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
     }
     return w;
   };
@@ -998,11 +994,11 @@ __device__ __forceinline__ void gram_pass_body(const WidePassArgs& a, const int 
   if (a.done && *a.done) return;
   if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
 
+  // (rows past m read a clamped row and are zeroed where the tile is put
+  // into LDS, so the loads stay in flight until then)
   auto load_h = [&](int64_t tile, d4 (&w)[H]) {
     const int64_t row = tile * 16 + x;
-    const bool row_ok = row < a.m;
-    const int64_t rowc = row_ok ? row : a.m - 1;
-    const uint64_t keep = row_ok ? ~0ull : 0ull;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
     for (int jj = 0; jj < H; ++jj) {
       // one descriptor per 16-column block
@@ -1012,9 +1008,7 @@ __device__ __forceinline__ void gram_pass_body(const WidePassArgs& a, const int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint32_t ow = (uint32_t)(((int64_t)(g + 4 * r) * a.ldw + rowc) * 8);
-        const uint64_t bits = __builtin_bit_cast(uint64_t,
-            __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
-        w[jj][r] = __builtin_bit_cast(double, bits & keep);
+        w[jj][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rw, (int)ow, 0, 0));
       }
     }
   };
@@ -1040,7 +1034,7 @@ __device__ __forceinline__ void gram_pass_body(const WidePassArgs& a, const int 
   Op* myop = ops + tw * NB * 4 * kOpSlot;
   for (int64_t s = s0; s < s1; ++s) {
     const int64_t tile = s * kWaves + tw;
-    const bool tile_ok = tile < tiles;
+    const bool tile_ok = tile < tiles && tile * 16 + x < a.m;   // this lane's row exists
     // this step's tile into LDS (operand order), then the next tile's loads
 #pragma unroll
     for (int jj = 0; jj < H; ++jj) {
