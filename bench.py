@@ -298,9 +298,12 @@ def _orth_invariants(A, Q, R, m, n):
 
 def _dominant_roofline(prof, m, n, precision):
     """Roofline object of the kernel kind with the larger total time among
-    the timed launches: HBM bytes per launch below 128 columns, FP64 MFMA
-    flops (m n^2 per apply or Gramian launch) from 128 columns on.  The mixed
-    form is measured on its FP64 apply launches."""
+    the timed launches: HBM bytes per launch below 80 columns, FP64 MFMA
+    flops from 80 columns on (a pass moves 16 m n bytes for 2 m n^2 flops, so
+    its intensity n / 8 passes the ridge of 78.6 TFLOP/s over 8 TB/s near
+    n = 79).  Flops: m n^2 per apply or Gramian of a pass, 2 m n^2 where one
+    launch does both.  The mixed form is measured on its FP64 apply
+    launches."""
     na, msa, bya = prof["apply"]
     ng, msg, byg = prof["gram"]
     kind = "apply" if (msa >= msg or precision == 1) else "gram"
@@ -318,8 +321,12 @@ def _dominant_roofline(prof, m, n, precision):
         names, fused = {"apply": "wide_pass (apply + Gramian)", "gram": "wide_pass (Gramian)"}, True
     else:
         names, fused = {"apply": "wide_apply", "gram": "gram_pass"}, False
-    if n >= 128:
+    if n >= 80:
         fpl = m * n * n * (2 if (fused and kind == "apply") else 1)
+        if n > 256 and precision == 0:
+            # one block_pass launch per 16-column block: a pass's flops are
+            # spread over ceil(n / 16) launches
+            fpl = fpl / ((n + 15) // 16)
         achieved = nl * fpl / (ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TF,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TF, 4), "traffic": None,
