@@ -47,6 +47,8 @@ typedef struct sqr_batch_item {
  *   items  per call; usage errors of one item (negative rc, with the checks
  *          of sqr_orth / sqr_append; SQR_EOPT also for a second append to the
  *          same basis in one batch) leave the other items running.
+ * Appends run on block_pass only: an append whose basis is too wide for it
+ * (see sqr_append) gets SQR_EDIM; run it with sqr_append.
  * An append with rc = SQR_OK and info.status = SQR_OK grows its basis by p;
  * on any other status the width is unchanged.  The call returns after the
  * work of the batch has finished on `stream` (the argument tables it stages

@@ -36,6 +36,10 @@ using namespace sqr;
 namespace {
 
 constexpr int kMaxSlots = 1024;
+// Largest column capacity of a handle (appends beyond kMaxSCols columns run
+// with the wide-basis route), and the bytes of cross_pass slots per handle.
+constexpr int64_t kMaxCap = 16384;
+constexpr size_t kCrossBudget = 512ull << 20;
 // Leading dimensions below 2^25 keep every per-lane buffer offset inside a
 // 16-column tile, (15 ld + m) * 8 bytes, below 4 GiB.
 constexpr int64_t kMaxLd = ((int64_t)1 << 25) - 1;
@@ -138,6 +142,11 @@ int64_t total_len(int64_t q, int64_t p) {
 int64_t e_off(int64_t q, int64_t J) { return 16 * (J * (round16(q) + 16) + 8 * J * (J - 1)); }
 int64_t bneg_off(int64_t q, int64_t J) { return 16 * (J * round16(q) + 8 * J * (J - 1)); }
 int64_t bneg_len(int64_t q, int64_t p) { return bneg_off(q, nblocks(p)); }
+// Widest basis an append with block p can have on block_pass (S = basis
+// tiles plus the block's tiles, at most kBlockTiles); wider bases take the
+// wide-basis route (mode 2 of small_step).
+int64_t q_fit(int64_t p) { return 16 * (int64_t)kBlockTiles - 16 * nblocks(p); }
+bool wide_basis(int64_t q, int64_t p) { return q > q_fit(p); }
 
 }  // namespace
 
@@ -165,6 +174,9 @@ struct sqr_basis {
   double *part = nullptr, *stage = nullptr;
   double *X = nullptr;
   double *bneg = nullptr, *rinv = nullptr;
+  // wide-basis appends: cross_pass slots, reduced B~, B~^T B~, R_old
+  int slots_c = 0;
+  double *partc = nullptr, *stage_bt = nullptr, *btb = nullptr, *rold = nullptr;
 };
 
 namespace {
@@ -218,6 +230,14 @@ const SplitVariant kSplit[] = {SQR_SPLIT(8), SQR_SPLIT(9), SQR_SPLIT(10), SQR_SP
                                SQR_SPLIT(13), SQR_SPLIT(14), SQR_SPLIT(15), SQR_SPLIT(16)};
 #undef SQR_SPLIT
 int g_split_occ[3][kSplitMax - kSplitMin + 1];   // [0 gram, 1 apply, 2 gram32][nb]
+
+// Wide-basis appends: cross_pass / proj_pass by block columns per tile (1..8).
+typedef void (*CrossKernel)(CrossArgs);
+typedef void (*ProjKernel)(ProjArgs);
+const CrossKernel kCross[8] = {cross_pass<1>, cross_pass<2>, cross_pass<3>, cross_pass<4>,
+                               cross_pass<5>, cross_pass<6>, cross_pass<7>, cross_pass<8>};
+const ProjKernel kProj[8] = {proj_pass<1>, proj_pass<2>, proj_pass<3>, proj_pass<4>,
+                             proj_pass<5>, proj_pass<6>, proj_pass<7>, proj_pass<8>};
 size_t split_lds_bytes(int nb, bool apply) {
   return 8 * (size_t)(apply ? apply_lds_doubles(nb) : gram_op_doubles(nb));
 }
@@ -275,6 +295,10 @@ void set_kernel_attributes_once() {
     lds_attr((const void*)v.apply_b, (int)split_lds_bytes(nb, true));
     lds_attr((const void*)v.gram_b, (int)split_lds_bytes(nb, false));
     lds_attr((const void*)v.gram32_b, (int)gram32_lds_bytes(nb));
+  }
+  for (int nb = 1; nb <= 8; ++nb) {
+    lds_attr((const void*)kCross[nb - 1], 8 * cross_lds_doubles(nb));
+    lds_attr((const void*)kProj[nb - 1], 8 * proj_lds_doubles(nb));
   }
   (void)hipGetLastError();
   int dev = 0;
@@ -334,35 +358,36 @@ void set_kernel_attributes_once() {
 }
 void set_kernel_attributes() { std::call_once(g_attr_once, set_kernel_attributes_once); }
 
-// Worst-case sizes over every call the handle can make (q + p <= cap).
-int64_t worst_total_len(int64_t cap) {
-  int64_t w = 0;
-  for (int64_t p = 1; p <= cap; ++p) w = std::max(w, total_len(cap - p, p));
-  return w;
-}
-int64_t worst_bneg_len(int64_t cap) {
-  int64_t w = 0;
-  for (int64_t p = 1; p <= cap; ++p) w = std::max(w, bneg_len(cap - p, p));
-  return w;
-}
+// Sizes (doubles) of the workspace regions of a handle; bt, pp and slots_c
+// are those of the wide-basis route (zero if the handle never takes it).
+struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp; int slots_c; };
 
-// Sizes (doubles) of the workspace regions of a handle.
-struct WsSizes { int64_t tl, arena, bneg, rinv; };
-
-// Every call a handle of capacity cap can make (q + p <= cap).
+// Every call a handle of capacity cap can make (q + p <= cap, p <= kMaxSCols):
+// on block_pass the sizes grow with q, so the widest basis that route takes
+// decides; the wide-basis route needs its block regions for q = 0 (covered)
+// and B~ for the widest basis.
 WsSizes handle_sizes(int64_t cap) {
-  WsSizes z;
-  z.tl = worst_total_len(cap);
-  z.arena = 0;
-  for (int64_t p = 1; p <= cap; ++p) z.arena = std::max<int64_t>(z.arena, small_arena((int)(cap - p), (int)p));
-  z.bneg = worst_bneg_len(cap);
-  z.rinv = nblocks(cap) * 256;
+  WsSizes z{0, 0, 0, 0, 0, 0, 0};
+  const int64_t pmax = std::min<int64_t>(cap, kMaxSCols);
+  for (int64_t p = 1; p <= pmax; ++p) {
+    const int64_t q1 = std::min(cap - p, q_fit(p));
+    z.tl = std::max(z.tl, total_len(q1, p));
+    z.arena = std::max<int64_t>(z.arena, small_arena((int)q1, (int)p));
+    z.bneg = std::max(z.bneg, bneg_len(q1, p));
+    if (wide_basis(cap - p, p)) {
+      z.bt = std::max(z.bt, round16(cap - p) * round16(p));
+      z.pp = std::max(z.pp, p * p);
+    }
+  }
+  z.rinv = nblocks(pmax) * 256;
+  if (z.bt > 0)
+    z.slots_c = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.bt))));
   return z;
 }
 
 // One orthogonalisation of n columns (no later appends).
 WsSizes orth_sizes(int64_t n) {
-  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256};
+  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0};
 }
 
 // Partial-Gram slots for m rows: one per resident workgroup at most, within
@@ -385,12 +410,22 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
   const size_t o_bneg = take(z.bneg);
   const size_t o_rinv = take(z.rinv);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
+  const bool wb = z.bt > 0;
+  const size_t o_partc = wb ? take((int64_t)z.slots_c * z.bt) : 0;
+  const size_t o_bt = wb ? take(z.bt) : 0;
+  const size_t o_btb = wb ? take(z.pp) : 0;
+  const size_t o_rold = wb ? take(z.pp) : 0;
   if (base) {
     b->slots = slots;
     b->part = base + o_part; b->stage = base + o_stage;
     b->X = base + o_X;
     b->bneg = base + o_bneg; b->rinv = base + o_rinv;
     b->ctrl = (Ctrl*)(base + o_ctrl);
+    b->slots_c = wb ? z.slots_c : 0;
+    b->partc = wb ? base + o_partc : nullptr;
+    b->stage_bt = wb ? base + o_bt : nullptr;
+    b->btb = wb ? base + o_btb : nullptr;
+    b->rold = wb ? base + o_rold : nullptr;
   }
   return doubles;
 }
@@ -433,7 +468,7 @@ int variant_index(const Variant* v) { return (int)(v - kVariants); }
 
 // One kernel launch of a pass, with its single-call and batched kernels.
 struct Launch {
-  enum Kind { kBlock, kWide, kReduce, kSmall } kind;
+  enum Kind { kBlock, kWide, kReduce, kSmall, kCross, kProj, kBtb, kBacc } kind;
   const void* k1;          // kernel of one call (arguments by value)
   const void* kb;          // the same kernel for a batch of calls
   union {
@@ -441,6 +476,10 @@ struct Launch {
     WidePassArgs wp;
     ReduceArgs ra;
     SmallArgs sa;
+    CrossArgs cr;
+    ProjArgs pj;
+    BtbArgs bb;
+    BaccArgs ba;
   } u;
   int64_t grid;            // workgroups of this call
   int threads;
@@ -455,6 +494,10 @@ size_t launch_arg_bytes(Launch::Kind k) {
     case Launch::kBlock: return sizeof(BlockPassArgs);
     case Launch::kWide: return sizeof(WidePassArgs);
     case Launch::kReduce: return sizeof(ReduceArgs);
+    case Launch::kCross: return sizeof(CrossArgs);
+    case Launch::kProj: return sizeof(ProjArgs);
+    case Launch::kBtb: return sizeof(BtbArgs);
+    case Launch::kBacc: return sizeof(BaccArgs);
     default: return sizeof(SmallArgs);
   }
 }
@@ -463,7 +506,11 @@ size_t launch_arg_bytes(Launch::Kind k) {
 // (by route), the fixed-order reduction of the slots, the small step.
 int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
   const int64_t P = nblocks(c.p);
-  const int64_t tl = total_len(c.q, c.p);
+  // wide basis: block_pass sees only the block (q = 0 layouts), the basis
+  // part runs in proj_pass / cross_pass / btb_pass / bacc_pass
+  const bool wideb = c.mode == 1 && wide_basis(c.q, c.p);
+  const int64_t qb = wideb ? 0 : c.q;
+  const int64_t tl = total_len(qb, c.p);
   const int64_t tiles = (b->m + 15) / 16;
   const bool apply = phase > 0;
   int64_t nwg = b->slots;
@@ -565,11 +612,31 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       join = true;
     }
   } else {
+    const int nb8 = (int)std::min<int64_t>(P, 8);
+    const int tiles_b = (int)((P + nb8 - 1) / nb8);
+    const int pitch = (int)round16(c.p), rows16 = (int)round16(c.q);
+    const double pass_bytes = 8.0 * (double)b->m * (double)(c.q + (apply ? 2 : 1) * c.p);
+    if (wideb && apply) {
+      // Z = W - Q_in B~ into the new columns (in place from pass 2 on)
+      Launch L;
+      memset(&L, 0, sizeof(L));
+      L.kind = Launch::kProj; L.k1 = (const void*)kProj[nb8 - 1]; L.kb = nullptr;
+      ProjArgs& a = L.u.pj;
+      a.win = (phase > 1) ? c.y : c.win; a.ldw = (phase > 1) ? c.ldy : c.ldw;
+      a.yout = c.y; a.ldy = c.ldy;
+      a.x = b->Q; a.ldx = b->ldq; a.nx = (int)c.q;
+      a.bt = b->stage_bt; a.pitch = pitch; a.rows16 = rows16;
+      a.p = (int)c.p; a.m = b->m; a.tiles_b = tiles_b;
+      a.done = &b->ctrl->done;
+      L.grid = ((b->m + 127) / 128) * tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
+      L.prof_kind = 1; L.prof_bytes = pass_bytes; L.prof_join = false;
+      out.push_back(L);
+    }
     // One grid size for every block of the pass (the slots are reduced
     // together): resident workgroups of the most demanding block's variant,
     // capped by the slot capacity and by the row tiles available.
     for (int64_t J = 0; J < P; ++J) {
-      const int ks = (int)round16(c.q) + (int)(16 * J);
+      const int ks = (int)round16(qb) + (int)(16 * J);
       const Variant* v = pick_variant((ks + 15) / 16);
       if (!v) return SQR_EDIM;
       const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
@@ -581,21 +648,23 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       Launch L;
       memset(&L, 0, sizeof(L));
       BlockPassArgs& a = L.u.bp;
-      const double* src = (apply && phase > 1) ? c.y : c.win;
-      const int64_t lds = (apply && phase > 1) ? c.ldy : c.ldw;
+      // (wide basis: the apply reads Z, which proj_pass left in the output)
+      const bool from_y = apply && (phase > 1 || wideb);
+      const double* src = from_y ? c.y : c.win;
+      const int64_t lds = from_y ? c.ldy : c.ldw;
       a.win = src + J * 16 * lds; a.ldw = lds;
       a.yout = c.y + J * 16 * c.ldy; a.ldy = c.ldy;
-      a.s1 = b->Q; a.ld1 = b->ldq; a.n1 = (int)c.q;
+      a.s1 = b->Q; a.ld1 = b->ldq; a.n1 = (int)qb;
       // same-pass prefix: new values after an apply, the input for the first Gram
       a.s2 = apply ? c.y : c.win; a.ld2 = apply ? c.ldy : c.ldw; a.n2 = (int)(16 * J);
       a.pb = (int)std::min<int64_t>(16, c.p - 16 * J);
       a.m = b->m;
-      a.bneg = b->bneg + bneg_off(c.q, J);
+      a.bneg = b->bneg + bneg_off(qb, J);
       a.rinv = b->rinv + 256 * J;
-      a.part = b->part; a.part_stride = tl; a.part_off = e_off(c.q, J);
+      a.part = b->part; a.part_stride = tl; a.part_off = e_off(qb, J);
       a.done = phase > 0 ? &b->ctrl->done : nullptr;  // phase 0 starts the call
       a.passes = &b->ctrl->passes;
-      a.copy_if_done = (phase == 1);
+      a.copy_if_done = (phase == 1) && !wideb;
       const int ks = (int)round16(a.n1) + a.n2;   // columns of S with the padding
       const Variant* v = pick_variant((ks + 15) / 16);
       L.kind = Launch::kBlock;
@@ -606,6 +675,32 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       // and (apply) the block written
       L.prof_kind = apply ? 1 : 0;
       L.prof_bytes = 8.0 * (double)b->m * (double)(a.n1 + a.n2 + (apply ? 2 : 1) * a.pb);
+      if (wideb) {
+        // one record for the whole pass of a wide-basis append
+        L.prof_join = apply || J > 0;
+        L.prof_bytes = pass_bytes;
+      }
+      out.push_back(L);
+    }
+    if (wideb) {
+      // B~ = Q_in^T Y (of W at phase 0), one row chunk per slot
+      Launch L;
+      memset(&L, 0, sizeof(L));
+      L.kind = Launch::kCross; L.k1 = (const void*)kCross[nb8 - 1]; L.kb = nullptr;
+      CrossArgs& a = L.u.cr;
+      a.x = b->Q; a.ldx = b->ldq; a.nx = (int)c.q;
+      a.y = apply ? c.y : c.win; a.ldy = apply ? c.ldy : c.ldw; a.ny = (int)c.p;
+      a.m = b->m;
+      a.pitch = pitch; a.rows16 = rows16;
+      a.tiles_b = tiles_b;
+      a.ntiles = (int)((rows16 + 16 * kCrossA - 1) / (16 * kCrossA)) * tiles_b;
+      const int64_t steps = (tiles + kWaves - 1) / kWaves;
+      const int64_t want = (1024 + a.ntiles - 1) / a.ntiles;
+      a.nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->slots_c, steps, want}));
+      a.part = b->partc; a.part_stride = (int64_t)rows16 * pitch;
+      a.done = phase > 0 ? &b->ctrl->done : nullptr;
+      L.grid = (int64_t)a.ntiles * a.nslots; L.threads = kGramThreads; L.lds = 8 * (size_t)cross_lds_doubles(nb8);
+      L.prof_kind = apply ? 1 : 0; L.prof_join = true;
       out.push_back(L);
     }
   }
@@ -621,13 +716,38 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     L.prof_kind = -1;
     out.push_back(L);
   }
+  if (wideb) {
+    // the cross_pass slots into B~, then B~^T B~
+    const Launch& X = out[out.size() - 2];   // the cross_pass launch
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kReduce; L.k1 = (const void*)reduce_slots; L.kb = (const void*)reduce_slots_batch;
+    ReduceArgs& r = L.u.ra;
+    r.in = b->partc; r.nslots = X.u.cr.nslots; r.stride = X.u.cr.part_stride; r.len = r.stride;
+    r.out = b->stage_bt;
+    r.done = phase > 0 ? &b->ctrl->done : nullptr;
+    L.grid = (r.len + kRedElems - 1) / kRedElems; L.threads = 64 * kRedWaves; L.lds = 0;
+    L.prof_kind = -1;
+    out.push_back(L);
+    Launch B;
+    memset(&B, 0, sizeof(B));
+    B.kind = Launch::kBtb; B.k1 = (const void*)btb_pass; B.kb = nullptr;
+    BtbArgs& t = B.u.bb;
+    t.bt = b->stage_bt; t.pitch = (int)round16(c.p); t.rows16 = (int)round16(c.q); t.p = (int)c.p;
+    t.out = b->btb;
+    t.done = phase > 0 ? &b->ctrl->done : nullptr;
+    B.grid = P * (P + 1) / 2; B.threads = kThreads; B.lds = 0;
+    B.prof_kind = -1;
+    out.push_back(B);
+  }
   {
     Launch L;
     memset(&L, 0, sizeof(L));
     L.kind = Launch::kSmall; L.k1 = (const void*)small_step; L.kb = (const void*)small_step_batch;
     SmallArgs& k = L.u.sa;
     k.E = b->stage;
-    k.mode = c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+    k.mode = wideb ? 2 : c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+    k.btb = b->btb; k.rold = b->rold;
     k.m = b->m; k.phase = phase;
     k.R = b->R; k.ldr = b->ldr;
     k.X = b->X;
@@ -638,11 +758,24 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
     k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
     k.mixed = mixed ? 1 : 0;
-    const size_t arena = 8 * (size_t)small_arena((int)c.q, (int)c.p);
+    const size_t arena = 8 * (size_t)small_arena((int)qb, (int)c.p);
     const size_t mbytes = 8 * (size_t)c.p * (size_t)c.p;
     k.lds_matrices = (arena <= g_small_lds) ? 1 : (mbytes <= g_small_lds ? 2 : 0);
     L.lds = k.lds_matrices == 1 ? arena : (k.lds_matrices == 2 ? mbytes : 0);
     L.grid = 1; L.threads = kSmallThreads;
+    L.prof_kind = -1;
+    out.push_back(L);
+  }
+  if (wideb) {
+    // B <- B + B~ R_old (phase 0: B <- B~), after the device's decision
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kBacc; L.k1 = (const void*)bacc_pass; L.kb = nullptr;
+    BaccArgs& a = L.u.ba;
+    a.bt = b->stage_bt; a.pitch = (int)round16(c.p); a.rold = b->rold;
+    a.R = b->R; a.ldr = b->ldr; a.q = (int)c.q; a.p = (int)c.p; a.phase = phase;
+    a.done = &b->ctrl->done;
+    L.grid = (nblocks(c.q) * P + kWaves - 1) / kWaves; L.threads = kThreads; L.lds = 0;
     L.prof_kind = -1;
     out.push_back(L);
   }
@@ -992,7 +1125,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   if (!out || !A || !Q || !R) return SQR_ENULL;
   if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap)
     return SQR_EDIM;
-  if (cap > kMaxSCols || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  if (n > kMaxSCols || cap > kMaxCap || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
   sqr_opts o;
   sqr_default_opts(&o);
   if (opts) o = *opts;
@@ -1067,7 +1200,8 @@ int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stream,
                sqr_info* info) {
   if (!b || !W) return SQR_ENULL;
-  if (p < 1 || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m) return SQR_EDIM;
+  if (p < 1 || p > kMaxSCols || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m)
+    return SQR_EDIM;
   if (!b->ws) {   // parked: take a workspace again
     const int rc0 = alloc_workspace(b);
     if (rc0) return rc0;
@@ -1104,9 +1238,9 @@ int sqr_batch(const sqr_opts* opts, sqr_batch_item* items, int32_t count, void* 
     } else if (it.kind == SQR_BATCH_APPEND) {
       sqr_basis* b = it.basis;
       if (!b || !it.in) it.rc = SQR_ENULL;
-      else if (it.cols < 1 || it.ld_in < b->m || it.ld_in > kMaxLd || b->n + it.cols > b->cap ||
-               b->n + it.cols > b->m)
-        it.rc = SQR_EDIM;
+      else if (it.cols < 1 || it.cols > kMaxSCols || it.ld_in < b->m || it.ld_in > kMaxLd ||
+               b->n + it.cols > b->cap || b->n + it.cols > b->m || wide_basis(b->n, it.cols))
+        it.rc = SQR_EDIM;   // (appends with a wide basis run through sqr_append only)
       for (int32_t k = 0; k < i && it.rc == SQR_OK; ++k)   // one call per handle
         if (items[k].kind == SQR_BATCH_APPEND && items[k].basis == b) it.rc = SQR_EOPT;
     } else {
@@ -1183,7 +1317,14 @@ int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const
   if (!out || !A || !Q || !R) return SQR_ENULL;
   if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap || r < 1 || r > n)
     return SQR_EDIM;
-  if (cap > kMaxSCols || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  if (cap > kMaxCap || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  // panel i holds columns [e_i, e_{i+1}), e_i = i n / r rounded to the
+  // nearest integer (ties to even), e_r = n; every panel within kMaxSCols
+  auto edge = [&](int64_t i) -> int64_t {
+    return (i >= r) ? n : (int64_t)nearbyint((double)i * ((double)n / (double)r));
+  };
+  for (int64_t i = 0; i < r; ++i)
+    if (edge(i + 1) - edge(i) > kMaxSCols) return SQR_EDIM;
   sqr_opts o;
   sqr_default_opts(&o);
   if (opts) o = *opts;
@@ -1196,11 +1337,9 @@ int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const
   int rc = alloc_workspace(b);
   if (rc) { sqr_free(b); return rc; }
   hipStream_t s = (hipStream_t)stream;
-  // panel i holds columns [e_i, e_{i+1}), e_i = i n / r rounded to the
-  // nearest integer (ties to even), e_r = n
   int64_t c0 = 0;
   for (int64_t i = 0; i < r; ++i) {
-    const int64_t c1 = (i + 1 == r) ? n : (int64_t)nearbyint((double)(i + 1) * ((double)n / (double)r));
+    const int64_t c1 = edge(i + 1);
     const int64_t p = c1 - c0;
     if (p < 1) continue;
     Call c{1, b->n, p, A + c0 * lda, lda, b->Q + b->n * b->ldq, b->ldq};
@@ -1251,6 +1390,7 @@ int sqr_park(sqr_basis* b) {
   }
   b->ws = nullptr; b->ws_bytes = 0; b->ctrl_host = nullptr; b->ctrl_host_dev = nullptr;
   b->ctrl = nullptr; b->part = b->stage = b->X = b->bneg = b->rinv = nullptr;
+  b->partc = b->stage_bt = b->btb = b->rold = nullptr;
   return SQR_OK;
 }
 

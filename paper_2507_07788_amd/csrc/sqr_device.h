@@ -70,6 +70,54 @@ struct ReduceArgs {
   int32_t nslots;
 };
 
+// Appends whose basis is too wide for block_pass's S (more than kBlockTiles
+// 16-column tiles with the block): the basis part of a pass runs as
+// GEMM-shaped launches.  B~ is kept row-major, rows16 = q rounded up to 16
+// rows of `pitch` = p rounded up to 16 doubles (padding rows and columns 0).
+constexpr int kBlockTiles = 36;
+
+// cross_pass: partial B~ = X^T Y over one row chunk per slot.
+struct CrossArgs {
+  const double* x; int64_t ldx; int32_t nx;   // m x nx basis (Q_in)
+  const double* y; int64_t ldy; int32_t ny;   // m x ny block
+  int64_t m;
+  double* part; int64_t part_stride;          // slot s: part + s * part_stride
+  int32_t pitch, rows16;
+  int32_t tiles_b;                            // column tiles of 16 NB
+  int32_t ntiles;                             // row tiles (of 128) * tiles_b
+  int32_t nslots;
+  const int32_t* done;                        // NULL in the initial Gram pass
+};
+
+// proj_pass: Z = W - X B~ (Z may be W).
+struct ProjArgs {
+  const double* win; int64_t ldw;
+  double* yout; int64_t ldy;
+  const double* x; int64_t ldx; int32_t nx;
+  const double* bt; int32_t pitch, rows16;
+  int32_t p;
+  int64_t m;
+  int32_t tiles_b;
+  const int32_t* done;
+};
+
+// btb_pass: out = B~^T B~ (p x p, row-major, both triangles).
+struct BtbArgs {
+  const double* bt; int32_t pitch, rows16, p;
+  double* out;
+  const int32_t* done;
+};
+
+// bacc_pass: B <- B + B~ R_old (B = R[0:q, q:q+p]); at phase 0 B <- B~ and
+// the block R[q:q+p, 0:q] <- 0.
+struct BaccArgs {
+  const double* bt; int32_t pitch;
+  const double* rold;                 // p x p row-major (upper triangular)
+  double* R; int64_t ldr;
+  int32_t q, p, phase;
+  const int32_t* done;
+};
+
 // Argument table of a batched launch: call c owns workgroups start[c] ..
 // start[c+1]-1 of the grid and reads args[c] (device memory).
 template <class T>
@@ -82,7 +130,8 @@ struct BatchTable {
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
   const double* E;       // reduced partial Gramians of the pass, block after block
-  int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2)
+  int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2),
+                         // 2 = append whose basis part runs in cross/proj/btb/bacc_pass
   int32_t q;             // basis width (append), 0 for orth
   int32_t p;             // block width being orthogonalised
   int32_t nblk;          // 16-column blocks of p
@@ -108,6 +157,10 @@ struct SmallArgs {
   int32_t mixed;         // orth in the mixed FP32/FP64 form
   int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X;
                          // 2: only the factor M (p x p) lives in LDS
+  // mode 2 (append with a wide basis): B~^T B~ from btb_pass, and where the
+  // old diagonal block of R goes for bacc_pass
+  const double* btb;
+  double* rold;
 };
 
 }  // namespace sqr

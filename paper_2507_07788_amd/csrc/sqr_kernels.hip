@@ -1094,6 +1094,331 @@ __global__ __launch_bounds__(kGramThreads) void gram_pass_batch(BatchTable<WideP
 
 
 // ---------------------------------------------------------------------------
+// Appends whose basis is too wide for block_pass's S (more than kBlockTiles
+// tiles with the block).  A pass of Algorithm 2 then runs as
+//   proj_pass    Z = W - Q_in B~ (apply phases): a tall product over the q
+//                basis columns, written into the new columns;
+//   block_pass   Y_J = Z_J D_J + Y_<J C_J and the Gramian G of Y (S holds only
+//                the block's own prefix, as for an orthogonalisation);
+//   cross_pass   B~ = Q_in^T Y, partial sums of one row chunk per slot;
+//   reduce_slots (G and B~), btb_pass (B~^T B~), small_step (mode 2), and
+//   bacc_pass    B <- B + B~ R_old.
+// Q_in is read twice per pass (proj and cross), not once per 16-column block.
+// ---------------------------------------------------------------------------
+constexpr int kCrossA = 8;   // basis blocks (16 columns) of a cross_pass tile
+__host__ __device__ constexpr int cross_lds_doubles(int nb) { return kWaves * (kCrossA + nb) * 4 * kOpSlot; }
+
+// Partial X^T Y of tile (128 basis columns) x (16 NB block columns) over the
+// rows of one slot, eight waves, 64-row steps staged in LDS in MFMA operand
+// order as in gram_pass; the 8 NB block pairs are dealt out to the waves.
+template <int NB>
+__device__ __forceinline__ void cross_pass_body(const CrossArgs& a, const int bid) {
+  extern __shared__ double lds[];
+  constexpr int NBLK = kCrossA + NB;               // blocks staged per row tile
+  constexpr int KP = NB;                           // pairs per wave (8 NB pairs)
+  constexpr int H = (NBLK + 1) / 2;                // blocks loaded per wave
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tw = wave >> 1, half = wave & 1;
+  const int x = lane & 15, g = lane >> 4;
+  const int slot = bid / a.ntiles, tile = bid - slot * a.ntiles;
+  const int ta = tile / a.tiles_b, tb = tile - ta * a.tiles_b;
+  const int a0 = 16 * kCrossA * ta, b0 = 16 * NB * tb;
+  const int64_t tiles = (a.m + 15) / 16;
+  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t per = (steps + a.nslots - 1) / a.nslots;
+  const int64_t s0 = (int64_t)slot * per;
+  const int64_t s1 = min(steps, s0 + per);
+
+  // blocks 0..7 are basis columns a0.., blocks 8.. block columns b0..; one
+  // descriptor per block (columns past the matrix read zero); rows past m
+  // read a clamped row and are zeroed where the tile goes into LDS
+  auto load_h = [&](int64_t t, d4 (&w)[H]) {
+    const int64_t row = t * 16 + x;
+    const int64_t rowc = row < a.m ? row : a.m - 1;
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) {
+      const int blk = half * H + jj;
+      const bool isx = blk < kCrossA;
+      const int c0 = isx ? a0 + 16 * blk : b0 + 16 * (blk - kCrossA);
+      const int nc = isx ? a.nx : a.ny;
+      const int64_t ld = isx ? a.ldx : a.ldy;
+      const int64_t nrec = (blk < NBLK && nc - 1 >= c0) ? (((int64_t)(nc - 1 - c0) * ld + a.m) * 8) : 0;
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc((isx ? a.x : a.y) + (int64_t)c0 * ld, nrec);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t o = (uint32_t)(((int64_t)(g + 4 * r) * ld + rowc) * 8);
+        w[jj][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)o, 0, 0));
+      }
+    }
+  };
+
+  d4 acc[KP];
+  int pi[KP], pj[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    const int pidx = wave + kGramWaves * k;
+    pi[k] = pidx / NB;
+    pj[k] = pidx - pi[k] * NB;
+  }
+  d4 wnext[H];
+  load_h(min(s0 * kWaves + tw, tiles - 1), wnext);
+  double* myop = lds + tw * NBLK * 4 * kOpSlot;
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t t = s * kWaves + tw;
+    const bool tile_ok = t < tiles && t * 16 + x < a.m;
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) {
+      const int blk = half * H + jj;
+      if (blk < NBLK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          myop[(blk * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = tile_ok ? wnext[jj][r] : 0.0;
+      }
+    }
+    load_h(min(t + kWaves, tiles - 1), wnext);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const double* oa = lds + pi[k] * 4 * kOpSlot + x + 17 * g;
+      const double* ob = lds + (kCrossA + pj[k]) * 4 * kOpSlot + x + 17 * g;
+#pragma unroll
+      for (int u4 = 0; u4 < kWaves; ++u4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[k] = mfma(oa[(u4 * NBLK * 4 + u) * kOpSlot], ob[(u4 * NBLK * 4 + u) * kOpSlot], acc[k]);
+    }
+    __syncthreads();
+  }
+  // lane (x, g) register r: B~[a0 + 16 I + g + 4r][b0 + 16 J + x]
+  double* out = a.part + (int64_t)slot * a.part_stride;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int col = b0 + 16 * pj[k] + x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = a0 + 16 * pi[k] + g + 4 * r;
+      if (row < a.rows16 && col < a.pitch) out[(int64_t)row * a.pitch + col] = acc[k][r];
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kGramThreads) void cross_pass(CrossArgs a) {
+  cross_pass_body<NB>(a, blockIdx.x);
+}
+
+// Z = W - X B~ for 128 rows (32 per wave, two 16-row tiles) x 16 NB columns.
+// B~ streams through LDS in chunks of kProjKC rows (double-buffered, one
+// barrier per chunk); the basis operand is loaded straight into registers,
+// one chunk ahead.  MFMA roles: A = B~ slice (from LDS), B = X rows, so the
+// result lane (x, g) register r is Z[row x][column g + 4r] (stores coalesce
+// along rows).
+constexpr int kProjKC = 32;
+__host__ __device__ constexpr int proj_pitch(int nb) { return 32 * ((16 * nb + 31) / 32) + 16; }
+__host__ __device__ constexpr int proj_lds_doubles(int nb) { return 2 * kProjKC * proj_pitch(nb); }
+
+template <int NB>
+__device__ __forceinline__ void proj_pass_body(const ProjArgs& a, const int bid) {
+  extern __shared__ double lds[];
+  constexpr int LP = proj_pitch(NB);
+  constexpr int SL = kProjKC / 4;                 // k-slices per chunk
+  constexpr int PER = 2 * NB;                     // B~ doubles per thread per chunk
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = lane & 15, g = lane >> 4;
+  const int rt = bid / a.tiles_b, tb = bid - rt * a.tiles_b;
+  const int b0 = 16 * NB * tb;
+  const int64_t rbase = (int64_t)rt * 128 + wave * 32;
+  const int nch = (a.rows16 + kProjKC - 1) / kProjKC;
+  int64_t rowc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) rowc[t] = min(rbase + 16 * t + x, a.m - 1);
+
+  // basis operand of chunk ch: lane (x, g), tile t, slice s holds
+  // X[row][k0 + 4s + g] (column clamped; zeroed at use past nx)
+  auto load_x = [&](int ch, double (&xv)[2][SL]) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int k = min(ch * kProjKC + 4 * s + g, a.nx - 1);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) xv[t][s] = a.x[(int64_t)k * a.ldx + rowc[t]];
+    }
+  };
+  // B~ chunk: thread -> row (tid >> 3) of the chunk, columns (tid & 7) * PER ..
+  const int brow = threadIdx.x >> 3, bcol = (threadIdx.x & 7) * PER;
+  auto load_b = [&](int ch, double (&bv)[PER]) {
+    const int k = min(ch * kProjKC + brow, a.rows16 - 1);
+#pragma unroll
+    for (int e = 0; e < PER; e += 2) {
+      const int c = min(b0 + bcol + e, a.pitch - 2);
+      const double2 v = *reinterpret_cast<const double2*>(a.bt + (int64_t)k * a.pitch + c);
+      bv[e] = v.x; bv[e + 1] = v.y;
+    }
+  };
+  auto store_b = [&](int ch, const double (&bv)[PER], double* buf) {
+    const bool rok = ch * kProjKC + brow < a.rows16;
+#pragma unroll
+    for (int e = 0; e < PER; ++e)
+      buf[brow * LP + bcol + e] = (rok && b0 + bcol + e < a.pitch) ? bv[e] : 0.0;
+  };
+  d4 acc[2][NB];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](int ch, const double (&xv)[2][SL], const double* buf) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const bool kok = ch * kProjKC + 4 * s + g < a.nx;
+      const double x0 = kok ? xv[0][s] : 0.0, x1 = kok ? xv[1][s] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double bv = buf[(4 * s + g) * LP + 16 * c + x];
+        acc[0][c] = mfma(bv, x0, acc[0][c]);
+        acc[1][c] = mfma(bv, x1, acc[1][c]);
+      }
+    }
+  };
+
+  double* buf0 = lds;
+  double* buf1 = lds + kProjKC * LP;
+  double xa[2][SL], xb[2][SL];
+  double bv[PER];
+  load_x(0, xa);
+  load_b(0, bv);
+  store_b(0, bv, buf0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ch += 2) {
+    if (ch + 1 < nch) { load_b(ch + 1, bv); load_x(ch + 1, xb); }
+    compute(ch, xa, buf0);
+    if (ch + 1 < nch) store_b(ch + 1, bv, buf1);
+    __syncthreads();
+    if (ch + 1 >= nch) break;
+    if (ch + 2 < nch) { load_b(ch + 2, bv); load_x(ch + 2, xa); }
+    compute(ch + 1, xb, buf1);
+    if (ch + 2 < nch) store_b(ch + 2, bv, buf0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t row = rbase + 16 * t + x;
+    if (row >= a.m) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double w[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = b0 + 16 * c + g + 4 * r;
+        w[r] = (col < a.p) ? a.win[(int64_t)col * a.ldw + row] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = b0 + 16 * c + g + 4 * r;
+        if (col < a.p) a.yout[(int64_t)col * a.ldy + row] = w[r] - acc[t][c][r];
+      }
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void proj_pass(ProjArgs a) {
+  proj_pass_body<NB>(a, blockIdx.x);
+}
+
+// B~^T B~: workgroup = one 16x16 block (I <= J) of the p x p result; wave w
+// sums the k-slices w, w + 4, ... (two chains), the four wave sums are added
+// in wave order; the block and its mirror are stored (exactly symmetric).
+__global__ __launch_bounds__(kThreads) void btb_pass(BtbArgs a) {
+  __shared__ double red[kWaves * 256];
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  int J = 0;
+  while ((J + 1) * (J + 2) / 2 <= (int)blockIdx.x) ++J;
+  const int I = (int)blockIdx.x - J * (J + 1) / 2;
+  const int nks = a.rows16 >> 2;
+  d4 c0 = d4{0.0, 0.0, 0.0, 0.0}, c1 = d4{0.0, 0.0, 0.0, 0.0};
+  int s = wave;
+  for (; s + kWaves < nks; s += 2 * kWaves) {
+    const double* r0 = a.bt + (int64_t)(4 * s + g) * a.pitch;
+    const double* r1 = a.bt + (int64_t)(4 * (s + kWaves) + g) * a.pitch;
+    const double a0 = r0[16 * I + x], b0v = r0[16 * J + x];
+    const double a1 = r1[16 * I + x], b1v = r1[16 * J + x];
+    c0 = mfma(a0, b0v, c0);
+    c1 = mfma(a1, b1v, c1);
+  }
+  if (s < nks) {
+    const double* r0 = a.bt + (int64_t)(4 * s + g) * a.pitch;
+    c0 = mfma(r0[16 * I + x], r0[16 * J + x], c0);
+  }
+  const d4 cw = c0 + c1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + r * 64 + lane] = cw[r];
+  __syncthreads();
+  if (wave != 0) return;
+  d4 sum = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum[r] += red[w * 256 + r * 64 + lane];
+  const int col = 16 * J + x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * I + g + 4 * r;
+    if (row < a.p && col < a.p && (I < J || row <= col)) {
+      a.out[(int64_t)row * a.p + col] = sum[r];
+      a.out[(int64_t)col * a.p + row] = sum[r];
+    }
+  }
+}
+
+// B <- B + B~ R_old in R[0:q, q:q+p]; one 16x16 block of B per wave.  At
+// phase 0 (R_old = I, B = 0): B <- B~, and R[q:q+p, 0:q] <- 0.
+__global__ __launch_bounds__(kThreads) void bacc_pass(BaccArgs a) {
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int P = (a.p + 15) >> 4, QT = (a.q + 15) >> 4;
+  const int blk = (int)blockIdx.x * kWaves + wave;
+  if (blk >= QT * P) return;
+  const int rb = blk / P, C = blk - rb * P;
+  const int row = 16 * rb + x;
+  if (a.phase == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = 16 * C + g + 4 * r;
+      if (row < a.q && col < a.p) {
+        a.R[row + (int64_t)(a.q + col) * a.ldr] = a.bt[(int64_t)row * a.pitch + col];
+        a.R[(a.q + col) + (int64_t)row * a.ldr] = 0.0;
+      }
+    }
+    return;
+  }
+  // R_old is upper triangular: rows k > 16 C + 15 contribute nothing
+  const int kend = min(16 * C + 16, a.pitch);
+  const int rowc = min(row, a.q - 1);
+  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const int k = k0 + g;
+    const double av = (k < a.p && 16 * C + x < a.p) ? a.rold[(int64_t)k * a.p + 16 * C + x] : 0.0;
+    const double bv = a.bt[(int64_t)rowc * a.pitch + k];
+    acc = mfma(av, bv, acc);
+  }
+  // lane (x, g) register r: (B~ R_old)[row][16 C + g + 4r]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int col = 16 * C + g + 4 * r;
+    if (row < a.q && col < a.p) a.R[row + (int64_t)(a.q + col) * a.ldr] += acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small_step: one workgroup of 256 threads finishes a pass.
 // ---------------------------------------------------------------------------
 constexpr int kSmallThreads = 256;
@@ -1440,7 +1765,11 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     for (int i = 0; i < 16; ++i) c->sigma[i] = 0.0;
   }
   const int p = a.p, q = a.q;
-  const int64_t pp = (int64_t)p * p, qp = (int64_t)q * p;
+  // mode 2: the basis part (B~, B~^T B~, B) lives outside this kernel; the
+  // Gramian blocks and C_J cover the block's own columns only
+  const bool wideb = a.mode == 2;
+  const int qe = wideb ? 0 : q;
+  const int64_t pp = (int64_t)p * p, qp = (int64_t)qe * p;
   double* base = lo ? lds : a.X;   // arena (LDS, or workspace)
   double* X = base;
   double* M = (a.lds_matrices == 2) ? lds : X + pp;   // mode 2: only M in LDS
@@ -1451,7 +1780,13 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   const int64_t ldr = a.ldr;
   const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
 
-  if (a.phase == 0) {
+  if (a.phase == 0 && wideb) {
+    // the diagonal block only (bacc_pass writes B and the block below R_in)
+    for (int e = tid; e < p * p; e += kSmallThreads) {
+      const int i = e % p, j = e / p;
+      R[roff + i + (int64_t)j * ldr] = (i == j) ? 1.0 : 0.0;
+    }
+  } else if (a.phase == 0) {
     // Algorithm 1: R = I.  Algorithm 2: B = 0, R = I_p, and the block below
     // the old R is zero in R_out (Prop. 2.1).
     for (int e = tid; e < (q + p) * p; e += kSmallThreads) {
@@ -1466,13 +1801,13 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
 
   // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
   //    G = E[q:q+p, :] (upper, mirrored).
-  const int q16 = (q + 15) & ~15;
+  const int q16 = (qe + 15) & ~15;
   const double* E = a.E;
   fill_rows(X, p, p, [&](int i, int j) {
     const int lo = min(i, j), hi = max(i, j);
     return E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
   });
-  fill_rows(Bt, q, p, [&](int i, int j) {
+  fill_rows(Bt, qe, p, [&](int i, int j) {
     return E[e_off(q16, j >> 4) + (int64_t)i * 16 + (j & 15)];
   });
   // old diagonal block of R and old B, loaded together with the Gramian
@@ -1488,6 +1823,11 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
   //    Upper triangle, each sum split over kSplit interleaved k-ranges whose
   //    partial sums are added in a fixed order; mirrored to the lower part.
+  if (wideb && q > 0) {
+    // B~^T B~ from btb_pass (symmetric, both triangles)
+    for (int e = tid; e < pp; e += kSmallThreads) X[e] -= a.btb[e];
+    wg_sync(lo);
+  }
   if (a.mode == 1 && q > 0) {
     constexpr int kSplit = 4;
     const bool split = pp * kSplit <= kMaxCols;
@@ -1855,6 +2195,13 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   //    At phase 0 (R_old = I, B_old = 0) both are copies.
   //    Fixed trip counts for p <= 16 (one row of B per thread, the row of
   //    B~ in registers; stores along columns of R coalesce).
+  if (wideb) {
+    // R_old for bacc_pass (the identity at phase 0)
+    for (int e = tid; e < pp; e += kSmallThreads) {
+      const int i = e / p, j = e % p;
+      a.rold[e] = ph0 ? (i == j ? 1.0 : 0.0) : Ro[e];
+    }
+  }
   if (ph0) {
     if (a.mode == 1)
       for (int e = tid; e < qp; e += kSmallThreads) {
@@ -1955,8 +2302,8 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     double* bn = a.bneg + 16 * ((int64_t)J * q16 + 8 * (int64_t)J * (J - 1));
     for (int kk = tid; kk < rows; kk += kSmallThreads) {
       double src[16];
-      const bool real = kk < q || kk >= q16;
-      const double* sr = (kk < q) ? Bt + (int64_t)kk * p + b0
+      const bool real = kk < qe || kk >= q16;
+      const double* sr = (kk < qe) ? Bt + (int64_t)kk * p + b0
                                   : (real ? M + (int64_t)(kk - q16) * p + b0 : Bt);
 #pragma unroll
       for (int t = 0; t < 16; ++t) src[t] = (real && t < pb) ? sr[t] : 0.0;

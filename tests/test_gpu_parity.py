@@ -480,6 +480,170 @@ def test_panel_parity(m, n, r, kappa):
 
 
 # --------------------------------------------------------------------------
+# appends with a wide basis (more S tiles than block_pass holds): the basis
+# part of each pass runs in proj_pass / cross_pass / btb_pass / bacc_pass
+# --------------------------------------------------------------------------
+def _grow(widths, m, kappas, seed, **kw):
+    """Orthogonalise the first panel and append the others, on the device
+    and in the oracle (on the device's own basis before each append, so the
+    comparison is per call).  Returns the device basis, the full input, and
+    the list of (device info, oracle info, oracle Q_out, oracle R_out)."""
+    mats = [S.test_matrix(m, w, k, seed=(seed, i)) for i, (w, k) in enumerate(zip(widths, kappas))]
+    cap = sum(widths)
+    b, info = sq.sqr_orth(dev(mats[0]), cap=cap, opts=sq.sqr_default_opts(**kw) if kw else None)
+    assert info["status"] == 0
+    steps = []
+    for Wm in mats[1:]:
+        q = b.n
+        Qin, Rin = host(b.q()), host(b.r())
+        Qo, Ro, io = O.append(Qin, Rin, Wm, **kw)
+        info = sq.sqr_append(b, dev(Wm, ld=m + 5))
+        steps.append((q, info, io, Qo, Ro))
+    return b, np.concatenate(mats, axis=1), steps
+
+
+@pytest.mark.parametrize("widths,kappas", [
+    ([500, 100], [1e3, 1e5]),             # q 500 > 464 = widest basis on block_pass for p = 100
+    ([300, 300, 37], [1e2, 1e4, 1e6]),    # two wide appends, ragged p
+    ([528, 40, 1], [1e3, 1e5, 1e2]),      # p = 1
+    ([400, 210, 130], [1e4, 1e8, 1e3]),   # p > 128: two column tiles in proj/cross
+    ([528, 528], [1e3, 1e3]),             # the widest block
+])
+def test_append_wide_basis_parity(widths, kappas):
+    """Each wide-basis append against the oracle's Algorithm 2 on the same
+    basis: the same status, passes within one, the new columns Q, the block
+    B = R[0:q, q:] and the diagonal block R[q:, q:] within the tolerances."""
+    m = 4007
+    b, A, steps = _grow(widths, m, kappas, seed=60)
+    for (q, info, io, Qo, Ro), kap in zip(steps, kappas[1:]):
+        p = Ro.shape[0] - q
+        assert info["status"] == io["status"] == 0, (q, p)
+        assert abs(info["passes"] - io["passes"]) <= 1
+    assert b.n == sum(widths)
+    Qg, Rg = host(b.q()), host(b.r())
+    assert O.loo(Qg) <= 1e-12 and O.rrr(A, Qg, Rg) <= 1e-13
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    # the last append element by element against the oracle on its basis
+    q, info, io, Qo, Ro = steps[-1]
+    tol = 1e-10 * kappas[-1]
+    for blk_g, blk_o in ((Rg[:q, q:], Ro[:q, q:]), (Rg[q:, q:], Ro[q:, q:]), (Qg[:, q:], Qo[:, q:])):
+        assert np.max(np.abs(blk_g - blk_o)) <= tol * max(np.linalg.norm(blk_o), 1.0)
+
+
+def test_append_wide_basis_element_wise_first_pass():
+    """One wide append of a well-conditioned block (kappa 10, no shift): B,
+    the new diagonal block of R and the new columns against the oracle
+    element by element at a tight tolerance (the arithmetic differs only in
+    the order of the summations)."""
+    m, q, p = 3001, 600, 24
+    A1 = S.test_matrix(m, 300, 10.0, seed=(61, 0))
+    A2 = S.test_matrix(m, 300, 10.0, seed=(61, 1))
+    W = S.test_matrix(m, p, 10.0, seed=(61, 2))
+    b, _ = sq.sqr_orth(dev(A1), cap=q + p)
+    assert sq.sqr_append(b, dev(A2))["status"] == 0 and b.n == q
+    Qin, Rin = host(b.q()), host(b.r())
+    Qo, Ro, io = O.append(Qin, Rin, W)
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == 0 and info["passes"] == io["passes"]
+    assert info["sigma"][:info["passes"]] == io["sigma"]
+    Rg, Qg = host(b.r()), host(b.q())
+    assert np.max(np.abs(Rg[:q, q:] - Ro[:q, q:])) <= 1e-13 * np.linalg.norm(Ro[:q, q:])
+    assert np.max(np.abs(Rg[q:, q:] - Ro[q:, q:])) <= 1e-13 * np.linalg.norm(Ro[q:, q:])
+    assert np.max(np.abs(Qg[:, q:] - Qo[:, q:])) <= 1e-12
+
+
+def test_append_wide_basis_nearly_dependent_shift():
+    """A block almost inside a 600-column basis: the unshifted factorisation
+    breaks down, the shift from ||X||_2 and its x10 escalation run on the
+    Schur complement that btb_pass and small_step form."""
+    m, q, p, eps = 3001, 600, 12, 1e-10
+    A1 = S.test_matrix(m, 300, 1e3, seed=(62, 0))
+    A2 = S.test_matrix(m, 300, 1e3, seed=(62, 1))
+    b, _ = sq.sqr_orth(dev(A1), cap=q + p)
+    assert sq.sqr_append(b, dev(A2))["status"] == 0
+    Qin, Rin = host(b.q()), host(b.r())
+    rng = np.random.default_rng(63)
+    W = Qin @ rng.standard_normal((q, p)) + eps * rng.standard_normal((m, p))
+    Qo, Ro, io = O.append(Qin, Rin, W)
+    assert io["status"] == 0 and io["chol_attempts"] > io["passes"]
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == 0 and b.n == q + p
+    assert abs(info["passes"] - io["passes"]) <= 1
+    assert abs(info["chol_attempts"] - io["chol_attempts"]) <= 1
+    Qg, Rg = host(b.q()), host(b.r())
+    A = np.concatenate([Qin @ Rin, W], axis=1)
+    assert O.loo(Qg) <= 1e-12 and O.rrr(A, Qg, Rg) <= 1e-13
+    Bo, Bg = Ro[:q, q:], Rg[:q, q:]
+    assert np.linalg.norm(Bg - Bo) <= 1e-8 * np.linalg.norm(Bo)
+
+
+@pytest.mark.parametrize("cap", [0, 2])
+def test_append_wide_basis_breakdown_keeps_width(cap):
+    """The exact breakdown of test_append_breakdown_keeps_width on a
+    600-column Hadamard basis (the wide-basis route): two identical new
+    columns orthogonal to the basis give X = m [[1, 1], [1, 1]]; with
+    u = 2^-100 every shift up to 100 sigma0 rounds away against m, so the
+    append ends with SQR_BREAKDOWN after 2 + cap factorisations, as in the
+    oracle; the width, Q and R are unchanged, and a NaN block then ends with
+    SQR_ENONFINITE, also keeping the width."""
+    k, q = 6, 600
+    m = 4 ** k
+    H = S.hadamard(m)
+    kw = dict(unit_roundoff=2.0 ** -100, max_escalations=cap)
+    opts = sq.sqr_default_opts(first_pass_shift=0, min_passes=0, **kw)
+    b, info = sq.sqr_orth(dev(H[:, :300] * 3.0), cap=q + 3, opts=opts)
+    assert info["status"] == 0
+    assert sq.sqr_append(b, dev(H[:, 300:q] * 3.0))["status"] == 0 and b.n == q
+    Q0, R0 = host(b.q()), host(b.r())
+    assert np.array_equal(Q0, H[:, :q] / 2.0 ** k) and np.array_equal(R0, 3.0 * 2.0 ** k * np.eye(q))
+    h = H[:, q]
+    W = np.asfortranarray(np.stack([h, h], axis=1))
+    _, _, io = O.append(Q0, R0, W, **kw)
+    assert io["status"] == O.BREAKDOWN and io["chol_attempts"] == 2 + cap
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == sq.SQR_BREAKDOWN
+    assert info["chol_attempts"] == io["chol_attempts"]
+    assert b.n == q
+    assert np.array_equal(host(b.q()), Q0) and np.array_equal(host(b.r()), R0)
+    Wn = H[:, q:q + 2].copy()
+    Wn[17, 1] = np.nan
+    _, _, io = O.append(Q0, R0, Wn, **kw)
+    assert io["status"] == O.ENONFINITE
+    info = sq.sqr_append(b, dev(Wn))
+    assert info["status"] == sq.SQR_ENONFINITE and b.n == q
+    # a regular block is then appended exactly: B = 0, R = 5 m^(1/2)
+    info = sq.sqr_append(b, dev(H[:, q + 1:q + 2] * 5.0))
+    assert info["status"] == 0 and b.n == q + 1
+    Rg = host(b.r())
+    assert np.array_equal(Rg[:q, q], np.zeros(q)) and Rg[q, q] == 5.0 * 2.0 ** k
+    assert np.array_equal(host(b.q())[:, q], H[:, q + 1] / 2.0 ** k)
+
+
+@pytest.mark.parametrize("m,n,r,kappa", [(3000, 800, 2, 1e4), (2500, 1200, 3, 1e6), (2000, 1100, 4, 1e3)])
+def test_panel_wide_parity(m, n, r, kappa):
+    """sqr_panel beyond 528 columns (panels of at most 528; from the second
+    panel on the basis is wide) against the oracle's Algorithm 3."""
+    A = S.test_matrix(m, n, kappa, seed=(66, r))
+    Qo, Ro, infos = O.panel(A, r)
+    assert all(i["status"] == O.OK for i in infos)
+    b, info = sq.sqr_panel(dev(A), r)
+    assert info["status"] == 0 and b.n == n
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+def test_batch_rejects_wide_basis_append():
+    """sqr_batch runs appends on block_pass only: an append whose basis is too
+    wide comes back with SQR_EDIM and leaves the basis as it was."""
+    m = 2000
+    A1 = S.test_matrix(m, 500, 1e2, seed=(67, 0))
+    b, _ = sq.sqr_orth(dev(A1), cap=600)
+    W = dev(S.test_matrix(m, 100, 1e2, seed=(67, 1)))
+    res = sq.sqr_batch([("append", b, W)])
+    assert res[0]["rc"] == sq.SQR_EDIM and b.n == 500
+    assert sq.sqr_append(b, W)["status"] == 0 and b.n == 600
+
+
+# --------------------------------------------------------------------------
 # batched calls (sqr_batch): the same results as the calls made alone
 # --------------------------------------------------------------------------
 def _alone_and_batched(specs, opts=None):
