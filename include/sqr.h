@@ -128,8 +128,13 @@ void sqr_default_opts(sqr_opts* o);
  * that stream wait for all work of the handle's previous call (an event),
  * so the calls of one handle are always ordered.  A handle must not be used
  * by two host threads at once.
- * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, n > 528, lda < m,
- * ldq < m, cap < n, ldr < cap, cap > 16384, lda or ldq > 2^25 - 1), SQR_EOPT (also for
+ * Widths: n up to cap (16384).  Blocks of more than 528 columns are applied
+ * in superblocks of 512 columns, their Gramian is formed as one matrix, and
+ * the small matrices (Cholesky, shift, R update) are worked on by one
+ * workgroup in the handle's workspace; the workspace grows with n (about
+ * 6 n^2 doubles beyond 528 columns).
+ * Errors: SQR_ENULL, SQR_EDIM (m < 1, n < 1, n > m, lda < m, ldq < m,
+ * cap < n, ldr < cap, cap > 16384, lda or ldq > 2^25 - 1), SQR_EOPT (also for
  * precision 1 with n > 256), SQR_EHIP; all
  * before any work is enqueued, except SQR_EHIP from a failed launch.
  */
@@ -179,13 +184,16 @@ int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A
  * may be NULL.  At least one pass runs, so the projection of Prop. 2.1 is
  * applied even when the initial Schur complement already passes the
  * stopping test (W = Q_in C + H, H orthonormal and orthogonal to Q_in).
- * Basis width: up to cap (16384).  While the basis and the block fit in 36
- * tiles of 16 columns (n rounded up to 16, plus p rounded up to 16, at most
- * 576), each pass streams Q_in once per 16-column block of W; a wider basis
- * takes the wide-basis route, which reads Q_in twice per pass (Q_in^T W and
- * W - Q_in B~ as separate tall products).  Both compute the same method.
- * Errors: SQR_ENULL, SQR_EDIM (p < 1, p > 528, ldw < m, ldw > 2^25 - 1,
- * n + p > cap, n + p > m).
+ * Widths: up to cap (16384).  While the basis and the block fit in 36 tiles
+ * of 16 columns (n rounded up to 16, plus p rounded up to 16, at most 576),
+ * each pass streams Q_in once per 16-column block of W; a wider basis takes
+ * the wide-basis route, which reads Q_in twice per pass (Q_in^T W and
+ * W - Q_in B~ as separate tall products).  A block of more than 528 columns
+ * is handled as in sqr_orth; the first such block larger than the handle's
+ * workspace serves makes the call wait for the handle's earlier work and
+ * take a larger workspace.  All routes compute the same method.
+ * Errors: SQR_ENULL, SQR_EDIM (p < 1, ldw < m, ldw > 2^25 - 1, n + p > cap,
+ * n + p > m).
  */
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,
                void* stream, sqr_info* info);
@@ -204,11 +212,9 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw,
  *            every panel waits for the device's decision).
  * On a non-zero status of panel i the handle keeps the basis of panels
  * 0..i-1 (sqr_cols tells its width) and the later panels are not run.
- * Widths: n up to cap (16384), every panel at most 528 columns (r >= n / 528
- * roughly); panels after the first run on a wide basis as sqr_append does.
- * Errors: as sqr_orth (without its n <= 528), and SQR_EDIM for r < 1,
- * r > n or a panel wider than 528 columns, SQR_EOPT for precision 1 (the
- * append always runs in FP64).
+ * Widths: n up to cap (16384), panels of any width (as sqr_append).
+ * Errors: as sqr_orth, and SQR_EDIM for r < 1 or r > n, SQR_EOPT for
+ * precision 1 (the append always runs in FP64).
  */
 int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const double* A, int64_t lda,
               int64_t r, double* Q, int64_t ldq, int64_t cap, double* R, int64_t ldr, void* stream,

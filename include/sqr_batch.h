@@ -48,7 +48,8 @@ typedef struct sqr_batch_item {
  *          of sqr_orth / sqr_append; SQR_EOPT also for a second append to the
  *          same basis in one batch) leave the other items running.
  * Appends run on block_pass only: an append whose basis is too wide for it
- * (see sqr_append) gets SQR_EDIM; run it with sqr_append.
+ * (see sqr_append) or whose block has more than 528 columns gets SQR_EDIM;
+ * run it with sqr_append.  Orthogonalisations take cap <= 528.
  * An append with rc = SQR_OK and info.status = SQR_OK grows its basis by p;
  * on any other status the width is unchanged.  The call returns after the
  * work of the batch has finished on `stream` (the argument tables it stages

@@ -177,6 +177,11 @@ struct sqr_basis {
   // wide-basis appends: cross_pass slots, reduced B~, B~^T B~, R_old
   int slots_c = 0;
   double *partc = nullptr, *stage_bt = nullptr, *btb = nullptr, *rold = nullptr;
+  // blocks wider than kMaxSCols (up to pbig columns): cross_pass slots of the
+  // Gramian, the reduced Gramian, R~ (row-major), vectors of the small step
+  int slots_g = 0;
+  int64_t pbig = 0;
+  double *partg = nullptr, *stage_g = nullptr, *rt = nullptr, *vec = nullptr;
 };
 
 namespace {
@@ -358,16 +363,18 @@ void set_kernel_attributes_once() {
 }
 void set_kernel_attributes() { std::call_once(g_attr_once, set_kernel_attributes_once); }
 
-// Sizes (doubles) of the workspace regions of a handle; bt, pp and slots_c
-// are those of the wide-basis route (zero if the handle never takes it).
-struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp; int slots_c; };
+// Sizes (doubles) of the workspace regions of a handle.  bt, pp and slots_c
+// serve appends with a wide basis; g, rt, vec and slots_g blocks wider than
+// kMaxSCols (zero where the handle never takes that route).
+struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp, g, rt, vec; int slots_c, slots_g; };
 
-// Every call a handle of capacity cap can make (q + p <= cap, p <= kMaxSCols):
-// on block_pass the sizes grow with q, so the widest basis that route takes
-// decides; the wide-basis route needs its block regions for q = 0 (covered)
-// and B~ for the widest basis.
-WsSizes handle_sizes(int64_t cap) {
-  WsSizes z{0, 0, 0, 0, 0, 0, 0};
+// Every call with a block of up to kMaxSCols columns a handle of capacity
+// cap can make (q + p <= cap): on block_pass the sizes grow with q, so the
+// widest basis that route takes decides; the wide-basis route needs its
+// block regions for q = 0 (covered) and B~ for the widest basis.  Blocks
+// wider than kMaxSCols are covered up to pbig columns (0: none).
+WsSizes handle_sizes(int64_t cap, int64_t pbig) {
+  WsSizes z{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t pmax = std::min<int64_t>(cap, kMaxSCols);
   for (int64_t p = 1; p <= pmax; ++p) {
     const int64_t q1 = std::min(cap - p, q_fit(p));
@@ -380,14 +387,34 @@ WsSizes handle_sizes(int64_t cap) {
     }
   }
   z.rinv = nblocks(pmax) * 256;
+  pbig = std::min(pbig, cap);
+  if (pbig > kMaxSCols) {
+    // superblocks on block_pass, the Gramian from cross_pass, the small
+    // matrices in the workspace; a basis beside the block at most cap - pbig
+    const int64_t p = pbig, p16 = round16(p);
+    z.tl = std::max(z.tl, total_len(0, kSuper));
+    z.arena = std::max<int64_t>(z.arena, small_arena(0, (int)p));
+    z.bneg = std::max<int64_t>(z.bneg, ((p + kSuper - 1) / kSuper) * kSuperBneg);
+    z.rinv = std::max(z.rinv, nblocks(p) * 256);
+    z.g = p16 * p16;
+    z.rt = p * p;
+    z.vec = p > kMaxCols ? 2 * p : 0;
+    if (cap - p > 0) {
+      // any block of more than kMaxSCols columns with a basis beside it
+      for (int64_t pb = kMaxSCols + 1; pb <= p; ++pb)
+        z.bt = std::max(z.bt, round16(cap - pb) * round16(pb));
+      z.pp = std::max(z.pp, p * p);
+    }
+    z.slots_g = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.g))));
+  }
   if (z.bt > 0)
     z.slots_c = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.bt))));
   return z;
 }
 
-// One orthogonalisation of n columns (no later appends).
+// One orthogonalisation of n <= kMaxSCols columns (no later appends).
 WsSizes orth_sizes(int64_t n) {
-  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0};
+  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0, 0, 0, 0, 0};
 }
 
 // Partial-Gram slots for m rows: one per resident workgroup at most, within
@@ -410,11 +437,15 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
   const size_t o_bneg = take(z.bneg);
   const size_t o_rinv = take(z.rinv);
   const size_t o_ctrl = take((sizeof(Ctrl) + 7) / 8);
-  const bool wb = z.bt > 0;
+  const bool wb = z.bt > 0, big = z.g > 0;
   const size_t o_partc = wb ? take((int64_t)z.slots_c * z.bt) : 0;
   const size_t o_bt = wb ? take(z.bt) : 0;
   const size_t o_btb = wb ? take(z.pp) : 0;
   const size_t o_rold = wb ? take(z.pp) : 0;
+  const size_t o_partg = big ? take((int64_t)z.slots_g * z.g) : 0;
+  const size_t o_g = big ? take(z.g) : 0;
+  const size_t o_rt = big ? take(z.rt) : 0;
+  const size_t o_vec = z.vec ? take(z.vec) : 0;
   if (base) {
     b->slots = slots;
     b->part = base + o_part; b->stage = base + o_stage;
@@ -426,12 +457,19 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
     b->stage_bt = wb ? base + o_bt : nullptr;
     b->btb = wb ? base + o_btb : nullptr;
     b->rold = wb ? base + o_rold : nullptr;
+    b->slots_g = big ? z.slots_g : 0;
+    b->partg = big ? base + o_partg : nullptr;
+    b->stage_g = big ? base + o_g : nullptr;
+    b->rt = big ? base + o_rt : nullptr;
+    b->vec = z.vec ? base + o_vec : nullptr;
   }
   return doubles;
 }
 
-int alloc_workspace(sqr_basis* b) {
-  const WsSizes z = handle_sizes(b->cap);
+// pbig: the widest block above kMaxSCols columns the workspace must serve
+// (0: none).
+int alloc_workspace(sqr_basis* b, int64_t pbig) {
+  const WsSizes z = handle_sizes(b->cap, pbig);
   const int slots = default_slots(b->m, z.tl);
   const size_t doubles = carve_workspace(b, nullptr, z, slots);
   {
@@ -446,6 +484,7 @@ int alloc_workspace(sqr_basis* b) {
     b->ws_bytes = doubles * 8;
   }
   carve_workspace(b, (double*)b->ws, z, slots);
+  b->pbig = z.g > 0 ? std::min(pbig, b->cap) : 0;
   if (!b->ctrl_host &&
       hipHostMalloc((void**)&b->ctrl_host, sizeof(Ctrl),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -502,9 +541,186 @@ size_t launch_arg_bytes(Launch::Kind k) {
   }
 }
 
+// Launches of one pass of a call whose block is wider than kMaxSCols columns
+// (p <= b->pbig): the apply in superblocks of kSuper columns, Z_K = W_K -
+// Q_in B~_K - Y_<K R~_<K,K by proj_pass, then block_pass on the superblock's
+// own 16-column blocks; the Gramian of the result (upper tiles) and, for an
+// append, B~ = Q_in^T Y by cross_pass; their fixed-order reductions,
+// btb_pass, small_step (full-Gramian form) and bacc_pass.
+int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
+  const int64_t P = nblocks(c.p), p16 = round16(c.p);
+  const bool apply = phase > 0;
+  const bool basis = c.mode == 1 && c.q > 0;
+  const int64_t m = b->m;
+  const int64_t tiles = (m + 15) / 16;
+  const int64_t steps64 = (tiles + kWaves - 1) / kWaves;
+  const int pitch_bt = (int)round16(c.p), rows_bt = (int)round16(c.q);
+  const double pass_bytes = 8.0 * (double)m * (double)(c.q + (apply ? 2 : 1) * c.p);
+  if (c.p > b->pbig || !b->stage_g || (basis && !b->stage_bt)) return SQR_EDIM;
+  bool first = true;   // the pass's streaming launches form one measured record
+  auto record = [&](Launch& L) {
+    L.prof_kind = apply ? 1 : 0; L.prof_bytes = pass_bytes; L.prof_join = !first;
+    first = false;
+  };
+  auto proj = [&](const double* win, int64_t ldw, double* yout, const double* x, int64_t ldx, int nx,
+                  const double* t, int64_t ldt, int rows16, int cols) {
+    const int nb8 = (int)std::min<int64_t>(nblocks(cols), 8);
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kProj; L.k1 = (const void*)kProj[nb8 - 1]; L.kb = nullptr;
+    ProjArgs& a = L.u.pj;
+    a.win = win; a.ldw = ldw; a.yout = yout; a.ldy = c.ldy;
+    a.x = x; a.ldx = ldx; a.nx = nx;
+    a.bt = t; a.ldt = ldt; a.rows16 = rows16;
+    a.p = cols; a.m = m;
+    a.tiles_b = (int)((nblocks(cols) + nb8 - 1) / nb8);
+    a.done = &b->ctrl->done;
+    L.grid = ((m + 127) / 128) * a.tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
+    record(L);
+    out.push_back(L);
+  };
+  if (apply) {
+    // where Z lives: the caller's block until something has been written
+    const bool from_y0 = phase > 1 || basis;
+    if (basis)
+      proj(phase > 1 ? c.y : c.win, phase > 1 ? c.ldy : c.ldw, c.y, b->Q, b->ldq, (int)c.q,
+           b->stage_bt, pitch_bt, rows_bt, (int)c.p);
+    for (int64_t k0 = 0; k0 < c.p; k0 += kSuper) {
+      const int64_t w = std::min<int64_t>(kSuper, c.p - k0), PK = nblocks(w);
+      const bool from_y = from_y0 || k0 > 0;
+      if (k0 > 0)
+        proj(from_y0 ? c.y + k0 * c.ldy : c.win + k0 * c.ldw, from_y0 ? c.ldy : c.ldw, c.y + k0 * c.ldy,
+             c.y, c.ldy, (int)k0, b->rt + k0, c.p, (int)k0, (int)w);
+      int64_t nwg = b->slots;
+      for (int64_t J = 0; J < PK; ++J) {
+        const Variant* v = pick_variant((int)J);
+        nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_occ[1][variant_index(v)]);
+        nwg = std::min<int64_t>(nwg, (tiles + (kWaves / v->wpt) - 1) / (kWaves / v->wpt));
+      }
+      nwg = std::max<int64_t>(nwg, 1);
+      for (int64_t Jl = 0; Jl < PK; ++Jl) {
+        const int64_t J = k0 / 16 + Jl;
+        Launch L;
+        memset(&L, 0, sizeof(L));
+        BlockPassArgs& a = L.u.bp;
+        const double* src = from_y ? c.y : c.win;
+        const int64_t lds = from_y ? c.ldy : c.ldw;
+        a.win = src + J * 16 * lds; a.ldw = lds;
+        a.yout = c.y + J * 16 * c.ldy; a.ldy = c.ldy;
+        a.s1 = c.y; a.ld1 = c.ldy; a.n1 = 0;
+        a.s2 = c.y + k0 * c.ldy; a.ld2 = c.ldy; a.n2 = (int)(16 * Jl);
+        a.pb = (int)std::min<int64_t>(16, c.p - 16 * J);
+        a.m = m;
+        a.bneg = b->bneg + (k0 / kSuper) * kSuperBneg + bneg_off(0, Jl);
+        a.rinv = b->rinv + 256 * J;
+        // (its Gramian partials are not used: the Gramian comes from cross_pass)
+        a.part = b->part; a.part_stride = total_len(0, kSuper); a.part_off = e_off(0, Jl);
+        a.done = &b->ctrl->done;
+        a.passes = &b->ctrl->passes;
+        a.copy_if_done = 0;
+        const Variant* v = pick_variant((int)Jl);
+        L.kind = Launch::kBlock;
+        L.k1 = (const void*)v->apply; L.kb = (const void*)v->apply_b;
+        L.grid = nwg; L.threads = kThreads; L.lds = block_lds_bytes(*v, true);
+        record(L);
+        out.push_back(L);
+      }
+    }
+  }
+  const double* src = apply ? c.y : c.win;
+  const int64_t lsrc = apply ? c.ldy : c.ldw;
+  auto cross = [&](const double* x, int64_t ldx, int nx, int rows16, int pitch, double* part, int slots_max,
+                   bool sym) -> int {
+    const int nb8 = (int)std::min<int64_t>(P, 8);
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kCross; L.k1 = (const void*)kCross[nb8 - 1]; L.kb = nullptr;
+    CrossArgs& a = L.u.cr;
+    a.x = x; a.ldx = ldx; a.nx = nx;
+    a.y = src; a.ldy = lsrc; a.ny = (int)c.p;
+    a.m = m; a.pitch = pitch; a.rows16 = rows16;
+    a.tiles_b = (int)((P + nb8 - 1) / nb8);
+    a.ntiles = (int)((rows16 + 16 * kCrossA - 1) / (16 * kCrossA)) * a.tiles_b;
+    const int64_t want = (1024 + a.ntiles - 1) / a.ntiles;
+    a.nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)slots_max, steps64, want}));
+    a.sym = sym ? 1 : 0;
+    a.part = part; a.part_stride = (int64_t)rows16 * pitch;
+    a.done = apply ? &b->ctrl->done : nullptr;
+    L.grid = (int64_t)a.ntiles * a.nslots; L.threads = kGramThreads; L.lds = 8 * (size_t)cross_lds_doubles(nb8);
+    record(L);
+    out.push_back(L);
+    return a.nslots;
+  };
+  const int ns_b = basis ? cross(b->Q, b->ldq, (int)c.q, rows_bt, pitch_bt, b->partc, b->slots_c, false) : 0;
+  const int ns_g = cross(src, lsrc, (int)c.p, (int)p16, (int)p16, b->partg, b->slots_g, true);
+  auto reduce = [&](const double* in, int nslots, int64_t len, double* dst) {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kReduce; L.k1 = (const void*)reduce_slots; L.kb = (const void*)reduce_slots_batch;
+    ReduceArgs& r = L.u.ra;
+    r.in = in; r.nslots = nslots; r.stride = len; r.len = len; r.out = dst;
+    r.done = apply ? &b->ctrl->done : nullptr;
+    L.grid = (len + kRedElems - 1) / kRedElems; L.threads = 64 * kRedWaves; L.lds = 0;
+    L.prof_kind = -1;
+    out.push_back(L);
+  };
+  if (basis) {
+    reduce(b->partc, ns_b, (int64_t)rows_bt * pitch_bt, b->stage_bt);
+    Launch B;
+    memset(&B, 0, sizeof(B));
+    B.kind = Launch::kBtb; B.k1 = (const void*)btb_pass; B.kb = nullptr;
+    BtbArgs& t = B.u.bb;
+    t.bt = b->stage_bt; t.pitch = pitch_bt; t.rows16 = rows_bt; t.p = (int)c.p;
+    t.out = b->btb;
+    t.done = apply ? &b->ctrl->done : nullptr;
+    B.grid = P * (P + 1) / 2; B.threads = kThreads; B.lds = 0;
+    B.prof_kind = -1;
+    out.push_back(B);
+  }
+  reduce(b->partg, ns_g, p16 * p16, b->stage_g);
+  {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kSmall; L.k1 = (const void*)small_step; L.kb = (const void*)small_step_batch;
+    SmallArgs& k = L.u.sa;
+    k.E = b->stage_g;
+    k.mode = c.mode; k.ext = 2 | (basis ? 1 : 0); k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+    k.btb = b->btb; k.rold = b->rold; k.rt = b->rt; k.vec = b->vec;
+    k.m = m; k.phase = phase;
+    k.R = b->R; k.ldr = b->ldr;
+    k.X = b->X;
+    k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+    k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256; k.publish_from = b->publish_from;
+    k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
+    k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
+    k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+    k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
+    k.mixed = 0;
+    k.lds_matrices = 0;   // the small matrices of a wide block live in the workspace
+    L.lds = 0;
+    L.grid = 1; L.threads = kSmallThreads;
+    L.prof_kind = -1;
+    out.push_back(L);
+  }
+  if (basis) {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kBacc; L.k1 = (const void*)bacc_pass; L.kb = nullptr;
+    BaccArgs& a = L.u.ba;
+    a.bt = b->stage_bt; a.pitch = pitch_bt; a.rold = b->rold;
+    a.R = b->R; a.ldr = b->ldr; a.q = (int)c.q; a.p = (int)c.p; a.phase = phase;
+    a.done = &b->ctrl->done;
+    L.grid = (nblocks(c.q) * P + kWaves - 1) / kWaves; L.threads = kThreads; L.lds = 0;
+    L.prof_kind = -1;
+    out.push_back(L);
+  }
+  return SQR_OK;
+}
+
 // The launches of pass `phase` of a call, in order: the streaming kernels
 // (by route), the fixed-order reduction of the slots, the small step.
 int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
+  if (c.p > kMaxSCols) return plan_big(b, c, phase, out);
   const int64_t P = nblocks(c.p);
   // wide basis: block_pass sees only the block (q = 0 layouts), the basis
   // part runs in proj_pass / cross_pass / btb_pass / bacc_pass
@@ -625,7 +841,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       a.win = (phase > 1) ? c.y : c.win; a.ldw = (phase > 1) ? c.ldy : c.ldw;
       a.yout = c.y; a.ldy = c.ldy;
       a.x = b->Q; a.ldx = b->ldq; a.nx = (int)c.q;
-      a.bt = b->stage_bt; a.pitch = pitch; a.rows16 = rows16;
+      a.bt = b->stage_bt; a.ldt = pitch; a.rows16 = rows16;
       a.p = (int)c.p; a.m = b->m; a.tiles_b = tiles_b;
       a.done = &b->ctrl->done;
       L.grid = ((b->m + 127) / 128) * tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
@@ -746,7 +962,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     L.kind = Launch::kSmall; L.k1 = (const void*)small_step; L.kb = (const void*)small_step_batch;
     SmallArgs& k = L.u.sa;
     k.E = b->stage;
-    k.mode = wideb ? 2 : c.mode; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+    k.mode = c.mode; k.ext = wideb ? 1 : 0; k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
     k.btb = b->btb; k.rold = b->rold;
     k.m = b->m; k.phase = phase;
     k.R = b->R; k.ldr = b->ldr;
@@ -1125,7 +1341,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   if (!out || !A || !Q || !R) return SQR_ENULL;
   if (m < 1 || n < 1 || n > m || lda < m || ldq < m || cap < n || ldr < cap)
     return SQR_EDIM;
-  if (n > kMaxSCols || cap > kMaxCap || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
+  if (cap > kMaxCap || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
   sqr_opts o;
   sqr_default_opts(&o);
   if (opts) o = *opts;
@@ -1136,7 +1352,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   b->m = m; b->n = n; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
   b->opts = o;
   (void)hipGetDevice(&b->device);
-  int rc = alloc_workspace(b);
+  int rc = alloc_workspace(b, n > kMaxSCols ? n : 0);
   if (rc) { sqr_free(b); return rc; }
   Call c{0, 0, n, A, lda, Q, ldq};
   hipStream_t s = (hipStream_t)stream;
@@ -1200,10 +1416,15 @@ int sqr_orth_noalloc(const sqr_opts* opts, int64_t m, int64_t n, const double* A
 int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stream,
                sqr_info* info) {
   if (!b || !W) return SQR_ENULL;
-  if (p < 1 || p > kMaxSCols || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m)
+  if (p < 1 || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m)
     return SQR_EDIM;
+  if (b->ws && p > kMaxSCols && p > b->pbig) {
+    // a wider block than the workspace serves: give it back (after the
+    // handle's queued work) and take one that fits
+    if (sqr_park(b)) return SQR_EHIP;
+  }
   if (!b->ws) {   // parked: take a workspace again
-    const int rc0 = alloc_workspace(b);
+    const int rc0 = alloc_workspace(b, p > kMaxSCols ? p : 0);
     if (rc0) return rc0;
     b->parked = false;
   }
@@ -1268,7 +1489,7 @@ int sqr_batch(const sqr_opts* opts, sqr_batch_item* items, int32_t count, void* 
       b->opts = o;
       b->device = device;
       b->noprof = true;
-      const int rc = alloc_workspace(b);
+      const int rc = alloc_workspace(b, 0);
       if (rc) { sqr_free(b); it.rc = rc; continue; }
       it.basis = b;
       c = Call{0, 0, it.cols, it.in, it.ld_in, it.Q, it.ldq};
@@ -1276,7 +1497,7 @@ int sqr_batch(const sqr_opts* opts, sqr_batch_item* items, int32_t count, void* 
     } else {
       b = it.basis;
       if (!b->ws) {
-        const int rc = alloc_workspace(b);
+        const int rc = alloc_workspace(b, 0);
         if (rc) { it.rc = rc; continue; }
         b->parked = false;
       }
@@ -1319,12 +1540,12 @@ int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const
     return SQR_EDIM;
   if (cap > kMaxCap || lda > kMaxLd || ldq > kMaxLd) return SQR_EDIM;
   // panel i holds columns [e_i, e_{i+1}), e_i = i n / r rounded to the
-  // nearest integer (ties to even), e_r = n; every panel within kMaxSCols
+  // nearest integer (ties to even), e_r = n
   auto edge = [&](int64_t i) -> int64_t {
     return (i >= r) ? n : (int64_t)nearbyint((double)i * ((double)n / (double)r));
   };
-  for (int64_t i = 0; i < r; ++i)
-    if (edge(i + 1) - edge(i) > kMaxSCols) return SQR_EDIM;
+  int64_t widest = 0;
+  for (int64_t i = 0; i < r; ++i) widest = std::max(widest, edge(i + 1) - edge(i));
   sqr_opts o;
   sqr_default_opts(&o);
   if (opts) o = *opts;
@@ -1334,7 +1555,7 @@ int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const
   b->m = m; b->n = 0; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
   b->opts = o;
   (void)hipGetDevice(&b->device);
-  int rc = alloc_workspace(b);
+  int rc = alloc_workspace(b, widest > kMaxSCols ? widest : 0);
   if (rc) { sqr_free(b); return rc; }
   hipStream_t s = (hipStream_t)stream;
   int64_t c0 = 0;
@@ -1391,6 +1612,8 @@ int sqr_park(sqr_basis* b) {
   b->ws = nullptr; b->ws_bytes = 0; b->ctrl_host = nullptr; b->ctrl_host_dev = nullptr;
   b->ctrl = nullptr; b->part = b->stage = b->X = b->bneg = b->rinv = nullptr;
   b->partc = b->stage_bt = b->btb = b->rold = nullptr;
+  b->partg = b->stage_g = b->rt = b->vec = nullptr;
+  b->pbig = 0;
   return SQR_OK;
 }
 

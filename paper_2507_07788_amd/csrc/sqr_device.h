@@ -9,6 +9,11 @@ namespace sqr {
 // number of columns of S (basis plus same-pass prefix) in one block launch.
 constexpr int kMaxCols = 1024;
 constexpr int kMaxSCols = 528;
+// Blocks wider than kMaxSCols are applied in superblocks of kSuper columns
+// (block_pass inside a superblock, proj_pass for the earlier ones); the C_J
+// of one superblock take kSuperBneg doubles (16-column blocks 0..31).
+constexpr int kSuper = 512;
+constexpr int64_t kSuperBneg = 16 * 8 * (int64_t)(kSuper / 16) * (kSuper / 16 - 1);
 
 // Device-resident state of one sqr_orth / sqr_append call.  Kernels read
 // `done` first and exit at once when it is set, so the host may enqueue more
@@ -86,15 +91,19 @@ struct CrossArgs {
   int32_t tiles_b;                            // column tiles of 16 NB
   int32_t ntiles;                             // row tiles (of 128) * tiles_b
   int32_t nslots;
+  int32_t sym;                                // X = Y: tiles strictly below the
+                                              // diagonal are skipped (not written)
   const int32_t* done;                        // NULL in the initial Gram pass
 };
 
-// proj_pass: Z = W - X B~ (Z may be W).
+// proj_pass: Z = W - X T (Z may be W), T row-major with row stride ldt:
+// rows16 rows (B~ of an append: q rounded up to 16, padding rows zero; a
+// superblock: the rows of R~ above it) and p columns.
 struct ProjArgs {
   const double* win; int64_t ldw;
   double* yout; int64_t ldy;
   const double* x; int64_t ldx; int32_t nx;
-  const double* bt; int32_t pitch, rows16;
+  const double* bt; int64_t ldt; int32_t rows16;
   int32_t p;
   int64_t m;
   int32_t tiles_b;
@@ -130,8 +139,7 @@ struct BatchTable {
 // One launch of small_step: finish a pass of an orth or append call.
 struct SmallArgs {
   const double* E;       // reduced partial Gramians of the pass, block after block
-  int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2),
-                         // 2 = append whose basis part runs in cross/proj/btb/bacc_pass
+  int32_t mode;          // 0 = orth (Algorithm 1, CholQR3 start), 1 = append (Algorithm 2)
   int32_t q;             // basis width (append), 0 for orth
   int32_t p;             // block width being orthogonalised
   int32_t nblk;          // 16-column blocks of p
@@ -157,10 +165,15 @@ struct SmallArgs {
   int32_t mixed;         // orth in the mixed FP32/FP64 form
   int32_t lds_matrices;  // 1: the small matrices live in LDS, not in X;
                          // 2: only the factor M (p x p) lives in LDS
-  // mode 2 (append with a wide basis): B~^T B~ from btb_pass, and where the
-  // old diagonal block of R goes for bacc_pass
+  // ext bit 0 (the basis part outside, an append with a wide basis):
+  // B~^T B~ from btb_pass, and where the old diagonal block of R goes for
+  // bacc_pass.  ext bit 1 (a block wider than kMaxSCols): E is one row-major
+  // Gramian, R~ is written to rt (row-major p x p) for proj_pass.
+  int32_t ext;
   const double* btb;
   double* rold;
+  double* rt;
+  double* vec;           // 2 p doubles for blocks wider than kMaxCols
 };
 
 }  // namespace sqr

@@ -1125,6 +1125,7 @@ __device__ __forceinline__ void cross_pass_body(const CrossArgs& a, const int bi
   const int slot = bid / a.ntiles, tile = bid - slot * a.ntiles;
   const int ta = tile / a.tiles_b, tb = tile - ta * a.tiles_b;
   const int a0 = 16 * kCrossA * ta, b0 = 16 * NB * tb;
+  if (a.sym && a0 >= b0 + 16 * NB) return;   // strictly below the diagonal
   const int64_t tiles = (a.m + 15) / 16;
   const int64_t steps = (tiles + kWaves - 1) / kWaves;
   const int64_t per = (steps + a.nslots - 1) / a.nslots;
@@ -1250,20 +1251,17 @@ __device__ __forceinline__ void proj_pass_body(const ProjArgs& a, const int bid)
   };
   // B~ chunk: thread -> row (tid >> 3) of the chunk, columns (tid & 7) * PER ..
   const int brow = threadIdx.x >> 3, bcol = (threadIdx.x & 7) * PER;
+  // (row and column clamped to the operand; zeroed where stored)
   auto load_b = [&](int ch, double (&bv)[PER]) {
     const int k = min(ch * kProjKC + brow, a.rows16 - 1);
 #pragma unroll
-    for (int e = 0; e < PER; e += 2) {
-      const int c = min(b0 + bcol + e, a.pitch - 2);
-      const double2 v = *reinterpret_cast<const double2*>(a.bt + (int64_t)k * a.pitch + c);
-      bv[e] = v.x; bv[e + 1] = v.y;
-    }
+    for (int e = 0; e < PER; ++e) bv[e] = a.bt[(int64_t)k * a.ldt + min(b0 + bcol + e, a.p - 1)];
   };
   auto store_b = [&](int ch, const double (&bv)[PER], double* buf) {
     const bool rok = ch * kProjKC + brow < a.rows16;
 #pragma unroll
     for (int e = 0; e < PER; ++e)
-      buf[brow * LP + bcol + e] = (rok && b0 + bcol + e < a.pitch) ? bv[e] : 0.0;
+      buf[brow * LP + bcol + e] = (rok && b0 + bcol + e < a.p) ? bv[e] : 0.0;
   };
   d4 acc[2][NB];
 #pragma unroll
@@ -1744,8 +1742,9 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   // power-iteration vectors, Schur partial sums, then (up to 8 blocks) the
   // inverted diagonal blocks D_J for forming C_J
   __shared__ double vw[2 * kMaxCols];
-  double* v = vw;
-  double* w = vw + kMaxCols;
+  // (blocks wider than kMaxCols keep the two vectors in global memory)
+  double* v = (a.p <= kMaxCols) ? vw : a.vec;
+  double* w = (a.p <= kMaxCols) ? vw + kMaxCols : a.vec + a.p;
   constexpr int kLdsDBlocks = 2 * kMaxCols / 256;
   __shared__ int cflag;
   Ctrl* c = a.ctrl;
@@ -1765,10 +1764,13 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     for (int i = 0; i < 16; ++i) c->sigma[i] = 0.0;
   }
   const int p = a.p, q = a.q;
-  // mode 2: the basis part (B~, B~^T B~, B) lives outside this kernel; the
-  // Gramian blocks and C_J cover the block's own columns only
-  const bool wideb = a.mode == 2;
-  const int qe = wideb ? 0 : q;
+  // outb: the basis part (B~, B~^T B~, B) lives outside this kernel; the
+  // Gramian blocks and C_J cover the block's own columns only.  fullE: the
+  // Gramian is one row-major matrix (pitch p rounded up to 16, upper part
+  // read), C_J are formed per superblock and R~ goes to a.rt.
+  const bool outb = (a.ext & 1) != 0;
+  const bool fullE = (a.ext & 2) != 0;
+  const int qe = outb ? 0 : q;
   const int64_t pp = (int64_t)p * p, qp = (int64_t)qe * p;
   double* base = lo ? lds : a.X;   // arena (LDS, or workspace)
   double* X = base;
@@ -1780,7 +1782,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   const int64_t ldr = a.ldr;
   const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
 
-  if (a.phase == 0 && wideb) {
+  if (a.phase == 0 && outb) {
     // the diagonal block only (bacc_pass writes B and the block below R_in)
     for (int e = tid; e < p * p; e += kSmallThreads) {
       const int i = e % p, j = e / p;
@@ -1803,9 +1805,11 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   //    G = E[q:q+p, :] (upper, mirrored).
   const int q16 = (qe + 15) & ~15;
   const double* E = a.E;
+  const int64_t epitch = (p + 15) & ~15;
   fill_rows(X, p, p, [&](int i, int j) {
     const int lo = min(i, j), hi = max(i, j);
-    return E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
+    return fullE ? E[(int64_t)lo * epitch + hi]
+                 : E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
   });
   fill_rows(Bt, qe, p, [&](int i, int j) {
     return E[e_off(q16, j >> 4) + (int64_t)i * 16 + (j & 15)];
@@ -1815,7 +1819,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   const bool ph0 = a.phase == 0;
   if (!ph0) {
     fill_rows(Ro, p, p, [&](int i, int j) { return R[roff + i + (int64_t)j * ldr]; });
-    if (a.mode == 1)
+    if (a.mode == 1 && !outb)
       fill_rows(Bo, q, p, [&](int i, int j) { return R[i + (int64_t)(q + j) * ldr]; });
   }
   // phase 0: the stores of R above precede the stores of step 6 by other threads
@@ -1823,12 +1827,12 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
   //    Upper triangle, each sum split over kSplit interleaved k-ranges whose
   //    partial sums are added in a fixed order; mirrored to the lower part.
-  if (wideb && q > 0) {
+  if (outb && q > 0) {
     // B~^T B~ from btb_pass (symmetric, both triangles)
     for (int e = tid; e < pp; e += kSmallThreads) X[e] -= a.btb[e];
     wg_sync(lo);
   }
-  if (a.mode == 1 && q > 0) {
+  if (a.mode == 1 && !outb && q > 0) {
     constexpr int kSplit = 4;
     const bool split = pp * kSplit <= kMaxCols;
     const int S = split ? kSplit : 1;
@@ -2195,7 +2199,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   //    At phase 0 (R_old = I, B_old = 0) both are copies.
   //    Fixed trip counts for p <= 16 (one row of B per thread, the row of
   //    B~ in registers; stores along columns of R coalesce).
-  if (wideb) {
+  if (outb && q > 0) {
     // R_old for bacc_pass (the identity at phase 0)
     for (int e = tid; e < pp; e += kSmallThreads) {
       const int i = e / p, j = e % p;
@@ -2203,7 +2207,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     }
   }
   if (ph0) {
-    if (a.mode == 1)
+    if (a.mode == 1 && !outb)
       for (int e = tid; e < qp; e += kSmallThreads) {
         const int i = e / p, j = e % p;
         R[i + (int64_t)(q + j) * ldr] = Bt[e];
@@ -2212,7 +2216,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
       const int i = e % p, j = e / p;
       R[roff + i + (int64_t)j * ldr] = (i <= j) ? M[(int64_t)i * p + j] : 0.0;
     }
-  } else if (a.mode == 1 && q > 0) {
+  } else if (a.mode == 1 && !outb && q > 0) {
     if (p <= 16) {
       for (int i = tid; i < q; i += kSmallThreads) {
         double br[16];
@@ -2295,16 +2299,23 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   //    streaming kernel forms Y_J = W_J D_J + [Q_in, Y_<J] C_J directly.
   //    One row of C_J per thread: the row of the source in registers, D_J
   //    read as broadcasts.
+  //    fullE: superblocks of kSuper columns, C_J = -R~[s0:16J, J] D_J with
+  //    s0 the first column of J's superblock (the earlier superblocks are
+  //    subtracted by proj_pass with R~ itself), each superblock's C_J from
+  //    its own region of bneg.
   for (int J = 0; J < a.nblk; ++J) {
     const int b0 = 16 * J, pb = min(16, p - b0);
-    const int rows = q16 + b0;
+    const int s0 = fullE ? (b0 / kSuper) * kSuper : 0;
+    const int Jl = J - s0 / 16;
+    const int rows = q16 + b0 - s0;
     const double* D = (a.nblk <= kLdsDBlocks) ? vw + J * 256 : a.rinv + J * 256;
-    double* bn = a.bneg + 16 * ((int64_t)J * q16 + 8 * (int64_t)J * (J - 1));
+    double* bn = a.bneg + (int64_t)(s0 / kSuper) * kSuperBneg +
+                 16 * ((int64_t)Jl * q16 + 8 * (int64_t)Jl * (Jl - 1));
     for (int kk = tid; kk < rows; kk += kSmallThreads) {
       double src[16];
       const bool real = kk < qe || kk >= q16;
       const double* sr = (kk < qe) ? Bt + (int64_t)kk * p + b0
-                                  : (real ? M + (int64_t)(kk - q16) * p + b0 : Bt);
+                                  : (real ? M + (int64_t)(s0 + kk - q16) * p + b0 : Bt);
 #pragma unroll
       for (int t = 0; t < 16; ++t) src[t] = (real && t < pb) ? sr[t] : 0.0;
 #pragma unroll
@@ -2320,6 +2331,13 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
         o.y = (cc + 1 < pb) ? v1 : 0.0;
         *reinterpret_cast<double2*>(bn + (int64_t)kk * 16 + cc) = o;
       }
+    }
+  }
+  if (fullE) {
+    // R~ for proj_pass (row-major, zero below the diagonal)
+    for (int64_t e = tid; e < pp; e += kSmallThreads) {
+      const int64_t i = e / p, j = e - i * p;
+      a.rt[e] = (i <= j) ? M[e] : 0.0;
     }
   }
   if (tid == 0) {

@@ -53,7 +53,6 @@ def test_usage_errors_before_any_gpu_work(sq):
     assert _orth(sq, 100, 10, 100, 99, 10, 10) == sq.SQR_EDIM     # ldq < m
     assert _orth(sq, 100, 10, 100, 100, 9, 10) == sq.SQR_EDIM     # cap < n
     assert _orth(sq, 100, 10, 100, 100, 12, 11) == sq.SQR_EDIM    # ldr < cap
-    assert _orth(sq, 10000, 600, 10000, 10000, 600, 600) == sq.SQR_EDIM  # n above 528
     assert _orth(sq, 40000, 10, 40000, 40000, 16385, 16385) == sq.SQR_EDIM  # cap above 16384
     bad = sq.sqr_default_opts(precision=7)
     assert _orth(sq, 100, 10, 100, 100, 10, 10, opts=bad) == sq.SQR_EOPT
@@ -172,8 +171,8 @@ def test_batch_usage_errors_before_any_gpu_work(sq):
 
 
 def test_panel_usage_errors_before_any_gpu_work(sq):
-    """sqr_panel (Algorithm 3) rejects r outside 1..n, panels wider than 528
-    columns, a capacity above 16384 and the mixed form before any HIP call."""
+    """sqr_panel (Algorithm 3) rejects r outside 1..n, a capacity above 16384
+    and the mixed form before any HIP call."""
     h = ctypes.c_void_p()
     P = lambda: ctypes.c_void_p(0x1000)   # never dereferenced
 
@@ -183,6 +182,5 @@ def test_panel_usage_errors_before_any_gpu_work(sq):
     assert panel(100, 10, 0) == sq.SQR_EDIM
     assert panel(100, 10, 11) == sq.SQR_EDIM
     assert panel(10, 11, 2) == sq.SQR_EDIM
-    assert panel(3000, 1100, 2) == sq.SQR_EDIM    # panels of 550 columns (above 528)
     assert panel(40000, 16385, 32) == sq.SQR_EDIM  # cap above 16384
     assert panel(100, 10, 2, sq.sqr_default_opts(precision=1)) == sq.SQR_EOPT

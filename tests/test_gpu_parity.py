@@ -644,6 +644,99 @@ def test_batch_rejects_wide_basis_append():
 
 
 # --------------------------------------------------------------------------
+# blocks wider than 528 columns: the apply in superblocks of 512 columns
+# (proj_pass for the earlier superblocks), the Gramian from cross_pass, the
+# small matrices of small_step in the workspace
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,kappa,variant", [
+    (3001, 529, 1e3, "CholQR3"), (4000, 600, 1e8, "CholQR3"), (3000, 1100, 1e5, "CholQR3"),
+    (2500, 700, 1e15, "CholQR3"), (3001, 800, 1e5, "rsCholQR"), (2000, 1030, 1e12, "rsCholQR"),
+])
+def test_orth_wide_block_parity(m, n, kappa, variant):
+    """sqr_orth beyond 528 columns against the oracle's Algorithm 1 (CholQR3
+    start, or as printed): the same status, passes within one, R and Q within
+    the tolerances (invariants only at kappa >= 1e12)."""
+    kw = {} if variant == "CholQR3" else dict(first_pass_shift=0, min_passes=0)
+    A = S.test_matrix(m, n, kappa, seed=(70, n))
+    Qo, Ro, io = O.orth(A, **kw)
+    b, info = sq.sqr_orth(dev(A, ld=m + 3), opts=sq.sqr_default_opts(**kw) if kw else None)
+    assert info["status"] == io["status"] == 0
+    assert abs(info["passes"] - io["passes"]) <= 1
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+@pytest.mark.parametrize("q,p,kappa", [(300, 600, 1e4), (17, 530, 1e6), (600, 1040, 1e3)])
+def test_append_wide_block_parity(q, p, kappa):
+    """An append of more than 528 columns on a basis (its B~, B~^T B~ and B
+    outside small_step) against the oracle's Algorithm 2 on the same basis."""
+    m = 3001
+    A1 = S.test_matrix(m, min(q, 300), 1e2, seed=(71, 0))
+    b, _ = sq.sqr_orth(dev(A1), cap=q + p)
+    if q > 300:
+        assert sq.sqr_append(b, dev(S.test_matrix(m, q - 300, 1e2, seed=(71, 1))))["status"] == 0
+    assert b.n == q
+    W = S.test_matrix(m, p, kappa, seed=(71, 2))
+    Qin, Rin = host(b.q()), host(b.r())
+    Qo, Ro, io = O.append(Qin, Rin, W)
+    info = sq.sqr_append(b, dev(W, ld=m + 1))
+    assert info["status"] == io["status"] == 0 and b.n == q + p
+    assert abs(info["passes"] - io["passes"]) <= 1
+    Qg, Rg = host(b.q()), host(b.r())
+    A = np.concatenate([Qin @ Rin, W], axis=1)
+    assert O.loo(Qg) <= 1e-12 and O.rrr(A, Qg, Rg) <= 1e-13
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    tol = 1e-10 * kappa
+    for blk_g, blk_o in ((Rg[:q, q:], Ro[:q, q:]), (Rg[q:, q:], Ro[q:, q:]), (Qg[:, q:], Qo[:, q:])):
+        assert np.max(np.abs(blk_g - blk_o)) <= tol * max(np.linalg.norm(blk_o), 1.0)
+
+
+@pytest.mark.parametrize("m,n,r,kappa", [(3000, 1200, 2, 1e5), (2500, 1100, 1, 1e4), (2000, 1600, 3, 1e5)])
+def test_panel_wide_block_parity(m, n, r, kappa):
+    """sqr_panel with panels wider than 528 columns (r = 1: one append of
+    1100 columns on an empty basis, wider than small_step's LDS vectors)
+    against the oracle's Algorithm 3."""
+    A = S.test_matrix(m, n, kappa, seed=(72, r))
+    Qo, Ro, infos = O.panel(A, r)
+    assert all(i["status"] == O.OK for i in infos)
+    b, info = sq.sqr_panel(dev(A), r)
+    assert info["status"] == 0 and b.n == n
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, kappa)
+
+
+def test_wide_block_breakdown_and_nonfinite_keep_width():
+    """A block of 542 columns whose first two columns are the same Hadamard
+    column: X has an exact zero pivot; with u = 2^-100 and no escalation the
+    append ends with SQR_BREAKDOWN after two factorisations, as in the
+    oracle, and the width is unchanged; a NaN block of 600 columns ends with
+    SQR_ENONFINITE; then a block of 600 Hadamard columns is appended exactly
+    (R~ = 64 I, so every step of the pass is exact in FP64)."""
+    k, q = 5, 16
+    m = 4 ** k
+    H = S.hadamard(m)
+    kw = dict(unit_roundoff=2.0 ** -100, max_escalations=0)
+    b, info = sq.sqr_orth(dev(H[:, :q] * 2.0), cap=q + 600,
+                          opts=sq.sqr_default_opts(first_pass_shift=0, min_passes=0, **kw))
+    assert info["status"] == 0
+    Q0, R0 = host(b.q()), host(b.r())
+    W = np.asfortranarray(np.concatenate([H[:, q:q + 1], H[:, q:q + 1], H[:, q + 1:q + 541]], axis=1))
+    _, _, io = O.append(Q0, R0, W, **kw)
+    assert io["status"] == O.BREAKDOWN and io["chol_attempts"] == 2
+    info = sq.sqr_append(b, dev(W))
+    assert info["status"] == sq.SQR_BREAKDOWN and info["chol_attempts"] == 2 and b.n == q
+    assert np.array_equal(host(b.q()), Q0) and np.array_equal(host(b.r()), R0)
+    Wn = H[:, q:q + 600].copy()
+    Wn[5, 333] = np.nan
+    info = sq.sqr_append(b, dev(Wn))
+    assert info["status"] == sq.SQR_ENONFINITE and b.n == q
+    info = sq.sqr_append(b, dev(H[:, q:q + 600] * 2.0))
+    assert info["status"] == 0 and b.n == q + 600
+    Rg = host(b.r())
+    assert np.array_equal(Rg[:q, q:], np.zeros((q, 600)))
+    assert np.array_equal(Rg[q:, q:], 2.0 * 2.0 ** k * np.eye(600))
+    assert np.array_equal(host(b.q()), H[:, :q + 600] / 2.0 ** k)
+
+
+# --------------------------------------------------------------------------
 # batched calls (sqr_batch): the same results as the calls made alone
 # --------------------------------------------------------------------------
 def _alone_and_batched(specs, opts=None):
