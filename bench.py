@@ -21,7 +21,7 @@ node 0 (at most 16 threads, the host share of one GPU), median of repeats.
 
 Other workloads: --workload orth (one orthogonalisation), serve (the full
 serving run), sweep (the m- and n-sweeps of Fig. 3b/3c at kappa 1e20), panel
-(the panel scheme against Algorithm 1, Fig. 4's shape up to n = 512).
+(the panel scheme against Algorithm 1, Fig. 4's shape up to n = 4096).
 
 Prints one JSON line (sweep: one line per point, then a summary line).
 --gpus N > 1 is refused: this program runs on one GPU.
@@ -285,8 +285,10 @@ def _orth_invariants(A, Q, R, m, n):
     G = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     res = nrm = 0.0
     Rt = torch.triu(R).contiguous()
-    for r0 in range(0, m, 1 << 22):
-        r1 = min(m, r0 + (1 << 22))
+    # row blocks of 2^16 rows: the evaluation's own rounding (a library GEMM
+    # summing over the block's rows) stays below the quantity it measures
+    for r0 in range(0, m, 1 << 16):
+        r1 = min(m, r0 + (1 << 16))
         Qb, Ab = Q[r0:r1].contiguous(), A[r0:r1].contiguous()
         G += Qb.t() @ Qb
         D = Ab - Qb @ Rt
@@ -604,21 +606,25 @@ def main_sweep(args):
                       "ok": all(r["ok"] for r in rows)}))
 
 
-PANEL_N = [128, 256, 384, 512]
+PANEL_N = [128, 256, 384, 512, 1024, 2048, 4096]
 
 
 def main_panel(args):
     """Fig. 4's comparison at m = 1e6, kappa = 1e5: Algorithm 1 as printed
     (rsCholQR: no first-pass shift, stopping test from the first pass), the
-    CholQR3 start, and the panel scheme with r = 2..5 panels, for n up to 512
-    (the library's width limit).  One JSON line per point, then a summary."""
+    CholQR3 start, and the panel scheme with r = 2..5 panels, for the n of
+    --panel-n.  One JSON line per point (ms per call), then a summary."""
     import torch
     import paper_2507_07788_amd as sq
     import synth
     m = 1_000_000
     rows = []
-    for n in PANEL_N:
+    ns = [int(v) for v in args.panel_n.split(",")] if args.panel_n else PANEL_N
+    for n in ns:
+        t0 = time.perf_counter()
         A = synth.test_matrix_device(m, n, 1e5, (50,))
+        torch.cuda.synchronize()
+        print(f"panel: n = {n} input in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         Q, R = sq.colmajor(m, n), sq.colmajor(n, n)
         variants = [("rsCholQR", None), ("CholQR3", None)] + [(f"pnCholQR({r})", r) for r in range(2, 6)]
         for name, r in variants:
@@ -666,6 +672,7 @@ def main():
                          "--precision); sweep: the m- and n-sweeps of Fig. 3b/3c; panel: the panel "
                          "scheme against Algorithm 1 (Fig. 4 shape)")
     ap.add_argument("--n", type=int, default=128, help="orth: columns")
+    ap.add_argument("--panel-n", type=str, default="", help="panel: comma-separated n (default 128..4096)")
     ap.add_argument("--kappa", type=float, default=1e12, help="orth: condition number")
     ap.add_argument("--precision", type=int, default=0, help="orth: 0 FP64, 1 mixed")
     ap.add_argument("--requests", type=int, default=10000, help="serve: requests")

@@ -399,11 +399,11 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
     z.g = p16 * p16;
     z.rt = p * p;
     z.vec = p > kMaxCols ? 2 * p : 0;
+    z.pp = std::max(z.pp, p * p);   // R_old (and B~^T B~ with a basis)
     if (cap - p > 0) {
       // any block of more than kMaxSCols columns with a basis beside it
       for (int64_t pb = kMaxSCols + 1; pb <= p; ++pb)
         z.bt = std::max(z.bt, round16(cap - pb) * round16(pb));
-      z.pp = std::max(z.pp, p * p);
     }
     z.slots_g = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.g))));
   }
@@ -440,8 +440,8 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
   const bool wb = z.bt > 0, big = z.g > 0;
   const size_t o_partc = wb ? take((int64_t)z.slots_c * z.bt) : 0;
   const size_t o_bt = wb ? take(z.bt) : 0;
-  const size_t o_btb = wb ? take(z.pp) : 0;
-  const size_t o_rold = wb ? take(z.pp) : 0;
+  const size_t o_btb = z.pp ? take(z.pp) : 0;
+  const size_t o_rold = z.pp ? take(z.pp) : 0;
   const size_t o_partg = big ? take((int64_t)z.slots_g * z.g) : 0;
   const size_t o_g = big ? take(z.g) : 0;
   const size_t o_rt = big ? take(z.rt) : 0;
@@ -455,8 +455,8 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
     b->slots_c = wb ? z.slots_c : 0;
     b->partc = wb ? base + o_partc : nullptr;
     b->stage_bt = wb ? base + o_bt : nullptr;
-    b->btb = wb ? base + o_btb : nullptr;
-    b->rold = wb ? base + o_rold : nullptr;
+    b->btb = z.pp ? base + o_btb : nullptr;
+    b->rold = z.pp ? base + o_rold : nullptr;
     b->slots_g = big ? z.slots_g : 0;
     b->partg = big ? base + o_partg : nullptr;
     b->stage_g = big ? base + o_g : nullptr;
@@ -507,7 +507,7 @@ int variant_index(const Variant* v) { return (int)(v - kVariants); }
 
 // One kernel launch of a pass, with its single-call and batched kernels.
 struct Launch {
-  enum Kind { kBlock, kWide, kReduce, kSmall, kCross, kProj, kBtb, kBacc } kind;
+  enum Kind { kBlock, kWide, kReduce, kSmall, kCross, kProj, kBtb, kBacc, kBig } kind;
   const void* k1;          // kernel of one call (arguments by value)
   const void* kb;          // the same kernel for a batch of calls
   union {
@@ -519,6 +519,7 @@ struct Launch {
     ProjArgs pj;
     BtbArgs bb;
     BaccArgs ba;
+    BigArgs bg;
   } u;
   int64_t grid;            // workgroups of this call
   int threads;
@@ -537,6 +538,7 @@ size_t launch_arg_bytes(Launch::Kind k) {
     case Launch::kProj: return sizeof(ProjArgs);
     case Launch::kBtb: return sizeof(BtbArgs);
     case Launch::kBacc: return sizeof(BaccArgs);
+    case Launch::kBig: return sizeof(BigArgs);
     default: return sizeof(SmallArgs);
   }
 }
@@ -678,30 +680,64 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
     out.push_back(B);
   }
   reduce(b->partg, ns_g, p16 * p16, b->stage_g);
-  {
+  // small_step in two stages around the band factorisation, then the R
+  // update and the operands of the next pass
+  SmallArgs k;
+  memset(&k, 0, sizeof(k));
+  k.E = b->stage_g;
+  k.mode = c.mode; k.ext = 2 | (basis ? 1 : 0); k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
+  k.btb = b->btb; k.rold = b->rold; k.rt = b->rt; k.vec = b->vec;
+  k.m = m; k.phase = phase;
+  k.R = b->R; k.ldr = b->ldr;
+  k.X = b->X;
+  k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+  k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256; k.publish_from = b->publish_from;
+  k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
+  k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
+  k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
+  k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
+  k.mixed = 0;
+  k.lds_matrices = 0;   // the small matrices of a wide block live in the workspace
+  auto small = [&](int stage) {
     Launch L;
     memset(&L, 0, sizeof(L));
     L.kind = Launch::kSmall; L.k1 = (const void*)small_step; L.kb = (const void*)small_step_batch;
-    SmallArgs& k = L.u.sa;
-    k.E = b->stage_g;
-    k.mode = c.mode; k.ext = 2 | (basis ? 1 : 0); k.q = (int)c.q; k.p = (int)c.p; k.nblk = (int)P;
-    k.btb = b->btb; k.rold = b->rold; k.rt = b->rt; k.vec = b->vec;
-    k.m = m; k.phase = phase;
-    k.R = b->R; k.ldr = b->ldr;
-    k.X = b->X;
-    k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
-    k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256; k.publish_from = b->publish_from;
-    k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
-    k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;
-    k.power_steps = b->opts.power_steps; k.tol = b->opts.tol; k.u = b->opts.unit_roundoff;
-    k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
-    k.mixed = 0;
-    k.lds_matrices = 0;   // the small matrices of a wide block live in the workspace
-    L.lds = 0;
-    L.grid = 1; L.threads = kSmallThreads;
+    L.u.sa = k;
+    L.u.sa.stage = stage;
+    L.lds = 0; L.grid = 1; L.threads = kSmallThreads;
     L.prof_kind = -1;
     out.push_back(L);
+  };
+  BigArgs g;
+  memset(&g, 0, sizeof(g));
+  g.X = b->X; g.M = b->X + (int64_t)c.p * c.p; g.p = (int)c.p; g.ctrl = b->ctrl;
+  g.rinv = b->rinv; g.rold = b->rold; g.R = b->R; g.ldr = b->ldr; g.q = (int)c.q; g.phase = phase;
+  g.rt = b->rt; g.bneg = b->bneg;
+  auto big = [&](const void* kern, int64_t grid, int threads, int k0) {
+    Launch L;
+    memset(&L, 0, sizeof(L));
+    L.kind = Launch::kBig; L.k1 = kern; L.kb = nullptr;
+    L.u.bg = g;
+    L.u.bg.k0 = k0;
+    L.grid = grid; L.threads = threads; L.lds = 0;
+    L.prof_kind = -1;
+    out.push_back(L);
+  };
+  small(1);
+  const int64_t tp = (c.p + 31) / 32;
+  big((const void*)mfill_pass, tp * tp, kThreads, 0);
+  for (int64_t k0 = 0; k0 < c.p; k0 += kBand) {
+    const int64_t k1 = std::min<int64_t>(c.p, k0 + kBand);
+    big((const void*)chol_diag, 1, kSmallThreads, (int)k0);
+    if (k1 < c.p) {
+      big((const void*)chol_panel, (c.p - k1 + kSmallThreads - 1) / kSmallThreads, kSmallThreads, (int)k0);
+      const int64_t T = (c.p - k1 + 15) / 16;
+      big((const void*)chol_trail, (T * (T + 1) / 2 + kWaves - 1) / kWaves, kThreads, (int)k0);
+    }
   }
+  small(2);
+  big((const void*)trmm_pass, (P * P + kWaves - 1) / kWaves, kThreads, 0);
+  big((const void*)cj_pass, P, kSmallThreads, 0);
   if (basis) {
     Launch L;
     memset(&L, 0, sizeof(L));

@@ -25,10 +25,13 @@ struct Ctrl {
   int32_t chol_attempts;  // factorisations tried, failed ones included
   int32_t converged;
   int32_t gram32;         // mixed form: the next pass forms an FP32 Gramian
-  int32_t pad[2];
+  int32_t chol_fail;      // blocks wider than kMaxSCols: the factorisation
+                          // run by the band kernels met a breakdown
+  int32_t att_shifted;    // ... and whether its diagonal was shifted
   double orth_fro;        // last ||X - I||_F
   double sigma[16];       // shift of each pass (0 = unshifted)
   double sigma_fixed;     // isCholQR: the shift of the input Gramian
+  double att_sigma;       // the shift of that factorisation
   int64_t stamp;          // host copy only: call id * 256 + phase of the last
                           // small_step that published this state
 };
@@ -127,6 +130,21 @@ struct BaccArgs {
   const int32_t* done;
 };
 
+// The kernels around small_step for blocks wider than kMaxSCols (p x p
+// row-major matrices in the workspace).
+struct BigArgs {
+  const double* X;        // the Schur complement (symmetric)
+  double* M;              // X + sigma I, then its upper Cholesky factor
+  int32_t p;
+  int32_t k0;             // chol_*: first row of the band
+  Ctrl* ctrl;
+  double* rinv;           // inverses of the 16x16 diagonal blocks
+  double* rold;           // R_old (the identity at phase 0)
+  double* R; int64_t ldr; int32_t q; int32_t phase;
+  double* rt;             // R~ row-major, zero below the diagonal
+  double* bneg;           // C_J per superblock
+};
+
 // Argument table of a batched launch: call c owns workgroups start[c] ..
 // start[c+1]-1 of the grid and reads args[c] (device memory).
 template <class T>
@@ -170,6 +188,11 @@ struct SmallArgs {
   // bacc_pass.  ext bit 1 (a block wider than kMaxSCols): E is one row-major
   // Gramian, R~ is written to rt (row-major p x p) for proj_pass.
   int32_t ext;
+  // blocks wider than kMaxSCols: 0 = the whole step; 1 = up to the shift of
+  // the first factorisation (the band kernels factor X + sigma I); 2 = from
+  // that factorisation's outcome on (further attempts in this workgroup; the
+  // R update and C_J by trmm_pass / cj_pass)
+  int32_t stage;
   const double* btb;
   double* rold;
   double* rt;

@@ -1754,7 +1754,7 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   int prev_att = 0;  // factorisations of earlier passes (thread 0)
   // mixed form: is the Gramian of this pass an FP32 one?
   const bool cur32 = (a.phase == 0) ? (a.mixed != 0) : (a.mixed != 0 && c->gram32 != 0);
-  if (a.phase > 0) {
+  if (a.phase > 0 || a.stage == 2) {
     if (c->done) return;
     if (tid == 0) prev_att = c->chol_attempts;
   } else if (tid == 0) {
@@ -1782,13 +1782,14 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   const int64_t ldr = a.ldr;
   const int64_t roff = q + (int64_t)q * ldr;  // R block at (q, q)
 
-  if (a.phase == 0 && outb) {
+  const bool front = a.stage != 2;   // this launch forms X and tests it
+  if (a.phase == 0 && outb && front) {
     // the diagonal block only (bacc_pass writes B and the block below R_in)
     for (int e = tid; e < p * p; e += kSmallThreads) {
       const int i = e % p, j = e / p;
       R[roff + i + (int64_t)j * ldr] = (i == j) ? 1.0 : 0.0;
     }
-  } else if (a.phase == 0) {
+  } else if (a.phase == 0 && front) {
     // Algorithm 1: R = I.  Algorithm 2: B = 0, R = I_p, and the block below
     // the old R is zero in R_out (Prop. 2.1).
     for (int e = tid; e < (q + p) * p; e += kSmallThreads) {
@@ -1801,71 +1802,73 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     }
   }
 
-  // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
-  //    G = E[q:q+p, :] (upper, mirrored).
   const int q16 = (qe + 15) & ~15;
   const double* E = a.E;
   const int64_t epitch = (p + 15) & ~15;
-  fill_rows(X, p, p, [&](int i, int j) {
-    const int lo = min(i, j), hi = max(i, j);
-    return fullE ? E[(int64_t)lo * epitch + hi]
-                 : E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
-  });
-  fill_rows(Bt, qe, p, [&](int i, int j) {
-    return E[e_off(q16, j >> 4) + (int64_t)i * 16 + (j & 15)];
-  });
-  // old diagonal block of R and old B, loaded together with the Gramian
-  // blocks (at phase 0 they are the identity and zero: step 6 then copies)
   const bool ph0 = a.phase == 0;
-  if (!ph0) {
-    fill_rows(Ro, p, p, [&](int i, int j) { return R[roff + i + (int64_t)j * ldr]; });
-    if (a.mode == 1 && !outb)
-      fill_rows(Bo, q, p, [&](int i, int j) { return R[i + (int64_t)(q + j) * ldr]; });
-  }
-  // phase 0: the stores of R above precede the stores of step 6 by other threads
-  wg_sync(lo && a.phase > 0);
-  // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
-  //    Upper triangle, each sum split over kSplit interleaved k-ranges whose
-  //    partial sums are added in a fixed order; mirrored to the lower part.
-  if (outb && q > 0) {
-    // B~^T B~ from btb_pass (symmetric, both triangles)
-    for (int e = tid; e < pp; e += kSmallThreads) X[e] -= a.btb[e];
-    wg_sync(lo);
-  }
-  if (a.mode == 1 && !outb && q > 0) {
-    constexpr int kSplit = 4;
-    const bool split = pp * kSplit <= kMaxCols;
-    const int S = split ? kSplit : 1;
-    for (int t = tid; t < pp * S; t += kSmallThreads) {
-      const int e = t / S, sg = t % S;
-      const int i = e / p, j = e % p;
-      if (i > j) continue;
-      double s = 0.0;
-#pragma unroll 8
-      for (int k = sg; k < q; k += S) s += Bt[(int64_t)k * p + i] * Bt[(int64_t)k * p + j];
-      if (split) {
-        v[t] = s;
-      } else {
-        X[e] -= s;
-        if (i != j) X[(int64_t)j * p + i] -= s;
-      }
+  if (front) {
+    // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
+    //    G = E[q:q+p, :] (upper, mirrored).
+    fill_rows(X, p, p, [&](int i, int j) {
+      const int lo = min(i, j), hi = max(i, j);
+      return fullE ? E[(int64_t)lo * epitch + hi]
+                   : E[e_off(q16, hi >> 4) + (int64_t)(q16 + lo) * 16 + (hi & 15)];
+    });
+    fill_rows(Bt, qe, p, [&](int i, int j) {
+      return E[e_off(q16, j >> 4) + (int64_t)i * 16 + (j & 15)];
+    });
+    // old diagonal block of R and old B, loaded together with the Gramian
+    // blocks (at phase 0 they are the identity and zero: step 6 then copies)
+    if (!ph0) {
+      fill_rows(Ro, p, p, [&](int i, int j) { return R[roff + i + (int64_t)j * ldr]; });
+      if (a.mode == 1 && !outb)
+        fill_rows(Bo, q, p, [&](int i, int j) { return R[i + (int64_t)(q + j) * ldr]; });
     }
-    wg_sync(lo);
-    if (split) {
-      for (int e = tid; e < pp; e += kSmallThreads) {
+    // phase 0: the stores of R above precede the stores of step 6 by other threads
+    wg_sync(lo && a.phase > 0);
+    // 2. Schur complement X = G - B~^T B~ (Prop. 2.1).
+    //    Upper triangle, each sum split over kSplit interleaved k-ranges whose
+    //    partial sums are added in a fixed order; mirrored to the lower part.
+    if (outb && q > 0) {
+      // B~^T B~ from btb_pass (symmetric, both triangles)
+      for (int e = tid; e < pp; e += kSmallThreads) X[e] -= a.btb[e];
+      wg_sync(lo);
+    }
+    if (a.mode == 1 && !outb && q > 0) {
+      constexpr int kSplit = 4;
+      const bool split = pp * kSplit <= kMaxCols;
+      const int S = split ? kSplit : 1;
+      for (int t = tid; t < pp * S; t += kSmallThreads) {
+        const int e = t / S, sg = t % S;
         const int i = e / p, j = e % p;
         if (i > j) continue;
         double s = 0.0;
-#pragma unroll
-        for (int sg = 0; sg < kSplit; ++sg) s += v[e * kSplit + sg];
-        X[e] -= s;
-        if (i != j) X[(int64_t)j * p + i] -= s;
+#pragma unroll 8
+        for (int k = sg; k < q; k += S) s += Bt[(int64_t)k * p + i] * Bt[(int64_t)k * p + j];
+        if (split) {
+          v[t] = s;
+        } else {
+          X[e] -= s;
+          if (i != j) X[(int64_t)j * p + i] -= s;
+        }
       }
       wg_sync(lo);
+      if (split) {
+        for (int e = tid; e < pp; e += kSmallThreads) {
+          const int i = e / p, j = e % p;
+          if (i > j) continue;
+          double s = 0.0;
+#pragma unroll
+          for (int sg = 0; sg < kSplit; ++sg) s += v[e * kSplit + sg];
+          X[e] -= s;
+          if (i != j) X[(int64_t)j * p + i] -= s;
+        }
+        wg_sync(lo);
+      }
     }
   }
-  // ||X||_2 by power iteration from the all-ones vector (D6 of the readings;
-  // Appendix A asks only for a rough estimate).  Every thread calls it and
+  // ||X||_2 by power iteration from the all-ones vector (the paper leaves the
+  // estimator open; Appendix A asks only for a rough estimate).  Every thread calls it and
   // receives the estimate.  On a copy of X in LDS when only M lives there: M
   // is rebuilt from X after each use.
   auto xnorm = [&]() -> double {
@@ -2098,23 +2101,23 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
     }
     return lam;
   };
-  // 3. ||X - I||_F.
+  // 3. ||X - I||_F (the second stage reads the first stage's value).
   double part = 0.0;
-  for (int i = tid >> 4; i < p; i += kSmallThreads / 16) {
+  for (int i = front ? (tid >> 4) : p; i < p; i += kSmallThreads / 16) {
 #pragma unroll 4
     for (int j = tid & 15; j < p; j += 16) {
       const double d = X[(int64_t)i * p + j] - (i == j ? 1.0 : 0.0);
       part += d * d;
     }
   }
-  const double err = sqrt(block_sum(part, red, lo));
+  const double err = front ? sqrt(block_sum(part, red, lo)) : c->orth_fro;
   // Shift policy of an orth call (appends always follow Algorithm 2):
   // 0 Algorithm 1 (recomputed from the current X, x10 escalation), 1 none
   // (a breakdown ends the call; a shifted first pass does not escalate),
   // 2 isCholQR (one shift from the input Gramian, reapplied on breakdown).
   const int pol = (a.mode == 0) ? a.shift_policy : 0;
   const double mm = (double)a.m;
-  if (pol == 2 && ph0 && isfinite(err)) {
+  if (pol == 2 && ph0 && isfinite(err) && front) {
     // ||X_0|| = ||A||^2: the one shift of the call
     const double lam0 = xnorm();
     if (tid == 0) c->sigma_fixed = fmax(11.0 * (mm * p + (double)p * (p + 1)) * a.u * lam0, 2.0 * a.u);
@@ -2123,7 +2126,9 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   //    first pass always runs: Prop. 2.1 forms the new columns by the
   //    projection, and an initial X = I does not make B~ zero).
   int status = -1;
-  if (!isfinite(err)) {
+  if (!front) {
+    // decided by the first stage
+  } else if (!isfinite(err)) {
     status = 3;  // SQR_ENONFINITE
   } else if ((a.mode == 0) ? (!cur32 && a.phase >= a.min_passes && err < a.tol)
                            : (a.phase >= 1 && err < a.tol)) {
@@ -2154,7 +2159,30 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
   const double ufl = cur32 ? kU32 : a.u;
   bool ok = false;
+  // stage 2: the first factorisation was run by the band kernels with the
+  // shift the first stage chose
+  bool ran = a.stage == 2;
+  if (ran) {
+    ok = c->chol_fail == 0;
+    shifted = c->att_shifted != 0;
+    sigma = c->att_sigma;
+    need_shift = false;
+    attempts = 1;
+  }
   for (;;) {
+    if (ran) {
+      ran = false;
+      if (ok) break;
+      if (!shifted) {
+        if (pol == 1) break;
+        need_shift = true;
+        continue;
+      }
+      if (pol != 0) break;
+      if (esc >= a.max_escalations) break;
+      ++esc;
+      sigma = fmax(10.0 * sigma, 2.0 * ufl);
+    }
     if (need_shift) {
       need_shift = false;
       shifted = true;
@@ -2169,6 +2197,16 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
         sigma = cur32 ? fmax((double)p * kU32 * lam, 2.0 * kU32)
                       : fmax(11.0 * cnt * a.u * lam, 2.0 * a.u);
       }
+    }
+    if (a.stage == 1) {
+      // the band kernels factor X + sigma I next
+      if (tid == 0) {
+        c->att_sigma = sigma;
+        c->att_shifted = shifted ? 1 : 0;
+        c->chol_fail = 0;
+        c->orth_fro = err;
+      }
+      return;
     }
     fill_rows(M, p, p, [&](int i, int j) { return X[(int64_t)i * p + j] + (i == j ? sigma : 0.0); });
     ++attempts;
@@ -2190,6 +2228,18 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
       c->chol_attempts = prev_att + attempts;
       c->orth_fro = err;
       c->done = 1;
+      publish(a, c);
+    }
+    return;
+  }
+  if (a.stage == 2) {
+    // the R update, C_J and R~ follow in trmm_pass and cj_pass
+    if (tid == 0) {
+      c->passes = pass;
+      c->gram32 = 0;
+      if (pass <= 16) c->sigma[pass - 1] = sigma;
+      c->chol_attempts = prev_att + attempts;
+      c->orth_fro = err;
       publish(a, c);
     }
     return;
@@ -2356,5 +2406,231 @@ __global__ __launch_bounds__(kSmallThreads) void small_step_batch(BatchTable<Sma
   small_step_body(t.args[blockIdx.x]);
 }
 
+// ---------------------------------------------------------------------------
+// Blocks wider than kMaxSCols: the p x p work of a pass on many workgroups.
+// small_step (stage 1) decides the stop test and the shift of the first
+// factorisation; mfill_pass forms X + sigma I and copies R_old; the upper
+// Cholesky factor is formed in bands of kBand rows (chol_diag: the diagonal
+// block by one workgroup, as small_step factors a block; chol_panel: the
+// band's rows right of it by forward substitution, one column per thread;
+// chol_trail: the trailing 16x16 blocks on MFMA), a breakdown stops the later
+// bands; small_step (stage 2) takes further attempts itself if needed; then
+// trmm_pass forms R <- R~ R_old and cj_pass the C_J and R~ of the next pass.
+// ---------------------------------------------------------------------------
+constexpr int kBand = 64;
+
+// M = X + sigma I and rold = R_old (row-major; the identity at phase 0),
+// 32 x 32 tiles (R_old is read along its columns and written along rows).
+__global__ __launch_bounds__(kThreads) void mfill_pass(BigArgs a) {
+  __shared__ double tile[32][33];
+  const Ctrl* c = a.ctrl;
+  if (c->done) return;
+  const int p = a.p;
+  const int tp = (p + 31) / 32;
+  const int ti = (int)blockIdx.x / tp, tj = (int)blockIdx.x % tp;
+  const double sigma = c->att_sigma;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ly; r < 32; r += 8) {
+    const int i = 32 * ti + r, j = 32 * tj + lx;
+    if (i < p && j < p) a.M[(int64_t)i * p + j] = a.X[(int64_t)i * p + j] + (i == j ? sigma : 0.0);
+  }
+  // R_old[i][j] = R[q + i + (q + j) ldr]: read with i along the lanes
+  for (int r = ly; r < 32; r += 8) {
+    const int j = 32 * tj + r, i = 32 * ti + lx;
+    double v = 0.0;
+    if (i < p && j < p) v = (a.phase == 0) ? (i == j ? 1.0 : 0.0) : a.R[(int64_t)(a.q + i) + (int64_t)(a.q + j) * a.ldr];
+    tile[r][lx] = v;
+  }
+  __syncthreads();
+  for (int r = ly; r < 32; r += 8) {
+    const int i = 32 * ti + r, j = 32 * tj + lx;
+    if (i < p && j < p) a.rold[(int64_t)i * p + j] = tile[lx][r];
+  }
+}
+
+// The diagonal block of band k0 (its upper part, as the earlier bands left
+// it) factored in LDS by one workgroup; the inverses of its 16x16 diagonal
+// blocks go to rinv.  A breakdown sets ctrl->chol_fail.
+__global__ __launch_bounds__(kSmallThreads) void chol_diag(BigArgs a) {
+  __shared__ double L[kBand * kBand];
+  __shared__ double blk[256];
+  __shared__ int flag;
+  Ctrl* c = a.ctrl;
+  if (c->done || c->chol_fail) return;
+  const int p = a.p, k0 = a.k0, w = min(kBand, p - k0);
+  for (int e = threadIdx.x; e < w * w; e += kSmallThreads) {
+    const int i = e / w, j = e - i * w;
+    L[e] = a.M[(int64_t)(k0 + i) * p + k0 + j];
+  }
+  __syncthreads();
+  const bool ok = chol_blocked(L, w, true, blk, &flag, a.rinv + 256 * (k0 / 16));
+  if (!ok) {
+    if (threadIdx.x == 0) c->chol_fail = 1;
+    return;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < w * w; e += kSmallThreads) {
+    const int i = e / w, j = e - i * w;
+    if (i <= j) a.M[(int64_t)(k0 + i) * p + k0 + j] = L[e];
+  }
+}
+
+// Rows k0 .. k0 + w - 1 right of the diagonal block: R_K,>K = R_KK^{-T}
+// M_K,>K, one column per thread (the order of operations of small_step's
+// blocked factorisation).
+__global__ __launch_bounds__(kSmallThreads) void chol_panel(BigArgs a) {
+  __shared__ double Rk[kBand * kBand];
+  const Ctrl* c = a.ctrl;
+  if (c->done || c->chol_fail) return;
+  const int p = a.p, k0 = a.k0, w = min(kBand, p - k0);
+  for (int e = threadIdx.x; e < w * w; e += kSmallThreads) {
+    const int i = e / w, j = e - i * w;
+    Rk[e] = a.M[(int64_t)(k0 + i) * p + k0 + j];
+  }
+  __syncthreads();
+  const int col = k0 + w + (int)blockIdx.x * kSmallThreads + (int)threadIdx.x;
+  if (col >= p) return;
+  double xc[kBand];
+#pragma unroll
+  for (int i = 0; i < kBand; ++i) xc[i] = (i < w) ? a.M[(int64_t)(k0 + i) * p + col] : 0.0;
+#pragma unroll
+  for (int i = 0; i < kBand; ++i) {
+    if (i < w) {
+      double s = xc[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= Rk[k * w + i] * xc[k];
+      xc[i] = s / Rk[i * w + i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kBand; ++i)
+    if (i < w) a.M[(int64_t)(k0 + i) * p + col] = xc[i];
+}
+
+// Trailing 16x16 blocks (I <= J) right of and below band k0:
+// M_IJ -= R_K,I^T R_K,J over the band's rows, one block per wave.
+__global__ __launch_bounds__(kThreads) void chol_trail(BigArgs a) {
+  const Ctrl* c = a.ctrl;
+  if (c->done || c->chol_fail) return;
+  const int p = a.p, k0 = a.k0, w = min(kBand, p - k0), k1 = k0 + w;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int T = (p - k1 + 15) >> 4;
+  const int64_t t = (int64_t)blockIdx.x * kWaves + wave;
+  if (t >= (int64_t)T * (T + 1) / 2) return;
+  int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)J * (J + 1) / 2 > t) --J;
+  while ((int64_t)(J + 1) * (J + 2) / 2 <= t) ++J;
+  const int I = (int)(t - (int64_t)J * (J + 1) / 2);
+  const int ci = k1 + 16 * I + x, cj = k1 + 16 * J + x;
+  d4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = k1 + 16 * I + g + 4 * r;
+    acc[r] = (row < p && cj < p) ? a.M[(int64_t)row * p + cj] : 0.0;
+  }
+  for (int s = 0; s < w; s += 4) {
+    const int k = k0 + s + g;
+    const bool kin = s + g < w;
+    const double av = (kin && ci < p) ? -a.M[(int64_t)k * p + ci] : 0.0;
+    const double bv = (kin && cj < p) ? a.M[(int64_t)k * p + cj] : 0.0;
+    acc = mfma(av, bv, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = k1 + 16 * I + g + 4 * r;
+    if (row < p && cj < p) a.M[(int64_t)row * p + cj] = acc[r];
+  }
+}
+
+// R[q:q+p, q:q+p] <- R~ R_old (upper times upper; zero below the diagonal),
+// one 16x16 block per wave.  The block of R~ in a row of blocks is turned
+// through a wave-private LDS tile so that both operands are read along rows.
+__global__ __launch_bounds__(kThreads) void trmm_pass(BigArgs a) {
+  __shared__ double trs[kWaves][16 * 17];
+  const Ctrl* c = a.ctrl;
+  if (c->done) return;
+  const int p = a.p, P = (p + 15) >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  const int64_t t = (int64_t)blockIdx.x * kWaves + wave;
+  if (t >= (int64_t)P * P) return;
+  const int I = (int)(t / P), J = (int)(t % P);   // block row I (of R~), column J
+  double* Rb = a.R + a.q + (int64_t)a.q * a.ldr;
+  double* tr = trs[wave];
+  if (I > J) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + x, col = 16 * J + g + 4 * r;
+      if (row < p && col < p) Rb[row + (int64_t)col * a.ldr] = 0.0;
+    }
+    return;
+  }
+  // D'[i][j] = newR[16 I + j][16 J + i]: A[i][k] = R_old[k][16 J + i],
+  // B[k][j] = R~[16 I + j][k]; lane (x, g) register r holds row 16 I + x,
+  // column 16 J + g + 4r
+  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  for (int K = I; K <= J; ++K) {
+    // R~ block (I, K) into LDS, masked to the upper triangle: tr[row][col]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + g + 4 * r, col = 16 * K + x;
+      tr[(g + 4 * r) * 17 + x] = (row < p && col < p && col >= row) ? a.M[(int64_t)row * p + col] : 0.0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * K + 4 * s + g;
+      const int col = 16 * J + x;
+      const double av = (k < p && col < p && k <= col) ? a.rold[(int64_t)k * p + col] : 0.0;
+      const double bv = tr[x * 17 + 4 * s + g];
+      acc = mfma(av, bv, acc);
+    }
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * I + x, col = 16 * J + g + 4 * r;
+    if (row < p && col < p) Rb[row + (int64_t)col * a.ldr] = (row <= col) ? acc[r] : 0.0;
+  }
+}
+
+// Per 16-column block J (one workgroup): C_J = -R~[s0:16J, J] D_J within
+// J's superblock (s0 its first column), as small_step forms it, and the
+// columns of J of R~ (row-major, zero below the diagonal) for proj_pass.
+__global__ __launch_bounds__(kSmallThreads) void cj_pass(BigArgs a) {
+  __shared__ double D[256];
+  const Ctrl* c = a.ctrl;
+  if (c->done) return;
+  const int p = a.p, J = blockIdx.x;
+  const int b0 = 16 * J, pb = min(16, p - b0);
+  const int s0 = (b0 / kSuper) * kSuper, Jl = J - s0 / 16;
+  for (int e = threadIdx.x; e < 256; e += kSmallThreads) D[e] = a.rinv[256 * J + e];
+  __syncthreads();
+  double* bn = a.bneg + (int64_t)(s0 / kSuper) * kSuperBneg + 128 * (int64_t)Jl * (Jl - 1);
+  for (int kk = threadIdx.x; kk < b0 - s0; kk += kSmallThreads) {
+    double src[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) src[t] = (t < pb) ? a.M[(int64_t)(s0 + kk) * p + b0 + t] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 16; cc += 2) {
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int t = 0; t <= cc + 1; ++t) {
+        if (t <= cc) v0 -= src[t] * D[t * 16 + cc];
+        v1 -= src[t] * D[t * 16 + cc + 1];
+      }
+      double2 o;
+      o.x = (cc < pb) ? v0 : 0.0;
+      o.y = (cc + 1 < pb) ? v1 : 0.0;
+      *reinterpret_cast<double2*>(bn + (int64_t)kk * 16 + cc) = o;
+    }
+  }
+  for (int i = threadIdx.x; i < p; i += kSmallThreads) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+      if (t < pb) a.rt[(int64_t)i * p + b0 + t] = (i <= b0 + t) ? a.M[(int64_t)i * p + b0 + t] : 0.0;
+  }
+}
 
 }  // namespace sqr
