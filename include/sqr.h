@@ -129,7 +129,7 @@ void sqr_default_opts(sqr_opts* o);
  * so the calls of one handle are always ordered.  A handle must not be used
  * by two host threads at once.
  * Widths: n up to cap (16384).  Blocks of more than 528 columns are applied
- * in superblocks of 512 columns, their Gramian is formed as one matrix, and
+ * in superblocks of 128 columns, their Gramian is formed as one matrix, and
  * the small matrices (Cholesky, shift, R update) are worked on by one
  * workgroup in the handle's workspace; the workspace grows with n (about
  * 6 n^2 doubles beyond 528 columns).

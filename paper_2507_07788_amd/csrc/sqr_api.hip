@@ -40,6 +40,10 @@ constexpr int kMaxSlots = 1024;
 // with the wide-basis route), and the bytes of cross_pass slots per handle.
 constexpr int64_t kMaxCap = 16384;
 constexpr size_t kCrossBudget = 512ull << 20;
+// bytes of cross_pass slots for the Gramian of a block wider than kMaxSCols
+constexpr size_t kGramBudget = 4ull << 30;
+// workgroups a cross_pass launch aims at (about eight per CU)
+constexpr int64_t kCrossWant = 2048;
 // Leading dimensions below 2^25 keep every per-lane buffer offset inside a
 // 16-column tile, (15 ld + m) * 8 bytes, below 4 GiB.
 constexpr int64_t kMaxLd = ((int64_t)1 << 25) - 1;
@@ -147,6 +151,10 @@ int64_t bneg_len(int64_t q, int64_t p) { return bneg_off(q, nblocks(p)); }
 // wide-basis route (mode 2 of small_step).
 int64_t q_fit(int64_t p) { return 16 * (int64_t)kBlockTiles - 16 * nblocks(p); }
 bool wide_basis(int64_t q, int64_t p) { return q > q_fit(p); }
+// Blocks that take the wide-block route (Gramian by cross_pass, apply in
+// superblocks): those wider than kMaxSCols.  (Between 256 and 528 columns
+// the per-block route measured faster or equal.)
+bool big_block(int64_t p) { return p > kMaxSCols; }
 
 }  // namespace
 
@@ -372,7 +380,7 @@ struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp, g, rt, vec; int slots_c,
 // cap can make (q + p <= cap): on block_pass the sizes grow with q, so the
 // widest basis that route takes decides; the wide-basis route needs its
 // block regions for q = 0 (covered) and B~ for the widest basis.  Blocks
-// wider than kMaxSCols are covered up to pbig columns (0: none).
+// on the wide-block route are covered up to pbig columns (0: none).
 WsSizes handle_sizes(int64_t cap, int64_t pbig) {
   WsSizes z{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t pmax = std::min<int64_t>(cap, kMaxSCols);
@@ -388,7 +396,7 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
   }
   z.rinv = nblocks(pmax) * 256;
   pbig = std::min(pbig, cap);
-  if (pbig > kMaxSCols) {
+  if (pbig > 0) {
     // superblocks on block_pass, the Gramian from cross_pass, the small
     // matrices in the workspace; a basis beside the block at most cap - pbig
     const int64_t p = pbig, p16 = round16(p);
@@ -405,7 +413,7 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
       for (int64_t pb = kMaxSCols + 1; pb <= p; ++pb)
         z.bt = std::max(z.bt, round16(cap - pb) * round16(pb));
     }
-    z.slots_g = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.g))));
+    z.slots_g = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kGramBudget / (8 * (size_t)z.g))));
   }
   if (z.bt > 0)
     z.slots_c = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(kCrossBudget / (8 * (size_t)z.bt))));
@@ -642,8 +650,11 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
     a.y = src; a.ldy = lsrc; a.ny = (int)c.p;
     a.m = m; a.pitch = pitch; a.rows16 = rows16;
     a.tiles_b = (int)((P + nb8 - 1) / nb8);
-    a.ntiles = (int)((rows16 + 16 * kCrossA - 1) / (16 * kCrossA)) * a.tiles_b;
-    const int64_t want = (1024 + a.ntiles - 1) / a.ntiles;
+    const int64_t ta = (rows16 + 16 * kCrossA - 1) / (16 * kCrossA);
+    a.ntiles = (int)(ta * a.tiles_b);
+    // tiles that work (sym: at or above the diagonal; 16 NB = 128 columns here)
+    const int64_t busy = sym ? ta * (ta + 1) / 2 : a.ntiles;
+    const int64_t want = (kCrossWant + busy - 1) / busy;
     a.nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)slots_max, steps64, want}));
     a.sym = sym ? 1 : 0;
     a.part = part; a.part_stride = (int64_t)rows16 * pitch;
@@ -756,7 +767,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
 // The launches of pass `phase` of a call, in order: the streaming kernels
 // (by route), the fixed-order reduction of the slots, the small step.
 int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
-  if (c.p > kMaxSCols) return plan_big(b, c, phase, out);
+  if (big_block(c.p)) return plan_big(b, c, phase, out);
   const int64_t P = nblocks(c.p);
   // wide basis: block_pass sees only the block (q = 0 layouts), the basis
   // part runs in proj_pass / cross_pass / btb_pass / bacc_pass
@@ -947,7 +958,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       a.tiles_b = tiles_b;
       a.ntiles = (int)((rows16 + 16 * kCrossA - 1) / (16 * kCrossA)) * tiles_b;
       const int64_t steps = (tiles + kWaves - 1) / kWaves;
-      const int64_t want = (1024 + a.ntiles - 1) / a.ntiles;
+      const int64_t want = (kCrossWant + a.ntiles - 1) / a.ntiles;
       a.nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->slots_c, steps, want}));
       a.part = b->partc; a.part_stride = (int64_t)rows16 * pitch;
       a.done = phase > 0 ? &b->ctrl->done : nullptr;
@@ -1388,7 +1399,7 @@ int sqr_orth(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n,
   b->m = m; b->n = n; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
   b->opts = o;
   (void)hipGetDevice(&b->device);
-  int rc = alloc_workspace(b, n > kMaxSCols ? n : 0);
+  int rc = alloc_workspace(b, big_block(n) ? n : 0);
   if (rc) { sqr_free(b); return rc; }
   Call c{0, 0, n, A, lda, Q, ldq};
   hipStream_t s = (hipStream_t)stream;
@@ -1454,13 +1465,13 @@ int sqr_append(sqr_basis* b, const double* W, int64_t p, int64_t ldw, void* stre
   if (!b || !W) return SQR_ENULL;
   if (p < 1 || ldw < b->m || ldw > kMaxLd || b->n + p > b->cap || b->n + p > b->m)
     return SQR_EDIM;
-  if (b->ws && p > kMaxSCols && p > b->pbig) {
+  if (b->ws && big_block(p) && p > b->pbig) {
     // a wider block than the workspace serves: give it back (after the
     // handle's queued work) and take one that fits
     if (sqr_park(b)) return SQR_EHIP;
   }
   if (!b->ws) {   // parked: take a workspace again
-    const int rc0 = alloc_workspace(b, p > kMaxSCols ? p : 0);
+    const int rc0 = alloc_workspace(b, big_block(p) ? p : 0);
     if (rc0) return rc0;
     b->parked = false;
   }
@@ -1591,7 +1602,7 @@ int sqr_panel(sqr_basis** out, const sqr_opts* opts, int64_t m, int64_t n, const
   b->m = m; b->n = 0; b->cap = cap; b->Q = Q; b->ldq = ldq; b->R = R; b->ldr = ldr;
   b->opts = o;
   (void)hipGetDevice(&b->device);
-  int rc = alloc_workspace(b, widest > kMaxSCols ? widest : 0);
+  int rc = alloc_workspace(b, big_block(widest) ? widest : 0);
   if (rc) { sqr_free(b); return rc; }
   hipStream_t s = (hipStream_t)stream;
   int64_t c0 = 0;

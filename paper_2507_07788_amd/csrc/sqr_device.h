@@ -12,7 +12,7 @@ constexpr int kMaxSCols = 528;
 // Blocks wider than kMaxSCols are applied in superblocks of kSuper columns
 // (block_pass inside a superblock, proj_pass for the earlier ones); the C_J
 // of one superblock take kSuperBneg doubles (16-column blocks 0..31).
-constexpr int kSuper = 512;
+constexpr int kSuper = 128;
 constexpr int64_t kSuperBneg = 16 * 8 * (int64_t)(kSuper / 16) * (kSuper / 16 - 1);
 
 // Device-resident state of one sqr_orth / sqr_append call.  Kernels read

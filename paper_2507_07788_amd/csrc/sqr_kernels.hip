@@ -1109,38 +1109,49 @@ constexpr int kCrossA = 8;   // basis blocks (16 columns) of a cross_pass tile
 __host__ __device__ constexpr int cross_lds_doubles(int nb) { return kWaves * (kCrossA + nb) * 4 * kOpSlot; }
 
 // Partial X^T Y of tile (128 basis columns) x (16 NB block columns) over the
-// rows of one slot, eight waves, 64-row steps staged in LDS in MFMA operand
-// order as in gram_pass; the 8 NB block pairs are dealt out to the waves.
+// rows of one slot, eight waves.  32-row steps (two 16-row tiles) are staged
+// in LDS in MFMA operand order, double-buffered: while the waves work on
+// step s from one buffer they store step s + 1 (loaded two steps earlier
+// into registers) into the other, so one barrier per step suffices and the
+// staging of one wave overlaps the MFMA work of the others.  Wave w owns the
+// WI x WJ block pairs (gi WI + i, gj WJ + j): per k-slice WI + WJ operand
+// reads from LDS feed WI WJ MFMAs.
 template <int NB>
 __device__ __forceinline__ void cross_pass_body(const CrossArgs& a, const int bid) {
   extern __shared__ double lds[];
   constexpr int NBLK = kCrossA + NB;               // blocks staged per row tile
   constexpr int KP = NB;                           // pairs per wave (8 NB pairs)
-  constexpr int H = (NBLK + 1) / 2;                // blocks loaded per wave
+  constexpr int HB = (NBLK + 3) / 4;               // blocks loaded per wave
+  constexpr int BUF = 2 * NBLK * 4 * kOpSlot;      // doubles of one buffer
+  constexpr int WI = (NB == 8) ? 2 : 1, WJ = NB / WI;
+  static_assert(WI * WJ == KP && (kCrossA / WI) * (NB / WJ) == kGramWaves, "pair split");
+  static_assert(2 * BUF == cross_lds_doubles(NB), "LDS size");
   if (a.done && *a.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int tw = wave >> 1, half = wave & 1;
+  const int tr = wave >> 2, qd = wave & 3;          // row tile of a step, block quarter
   const int x = lane & 15, g = lane >> 4;
   const int slot = bid / a.ntiles, tile = bid - slot * a.ntiles;
   const int ta = tile / a.tiles_b, tb = tile - ta * a.tiles_b;
   const int a0 = 16 * kCrossA * ta, b0 = 16 * NB * tb;
   if (a.sym && a0 >= b0 + 16 * NB) return;   // strictly below the diagonal
   const int64_t tiles = (a.m + 15) / 16;
-  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t steps = (tiles + 1) / 2;
   const int64_t per = (steps + a.nslots - 1) / a.nslots;
   const int64_t s0 = (int64_t)slot * per;
   const int64_t s1 = min(steps, s0 + per);
+  const int gi = wave % (kCrossA / WI), gj = wave / (kCrossA / WI);
 
-  // blocks 0..7 are basis columns a0.., blocks 8.. block columns b0..; one
-  // descriptor per block (columns past the matrix read zero); rows past m
-  // read a clamped row and are zeroed where the tile goes into LDS
-  auto load_h = [&](int64_t t, d4 (&w)[H]) {
+  // blocks qd, qd + 4, ... of row tile t: blocks 0..7 are basis columns a0..,
+  // blocks 8.. block columns b0..; one descriptor per block (columns past the
+  // matrix read zero); rows past m read a clamped row and are zeroed where
+  // the tile goes into LDS
+  auto load = [&](int64_t t, d4 (&w)[HB]) {
     const int64_t row = t * 16 + x;
     const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
-    for (int jj = 0; jj < H; ++jj) {
-      const int blk = half * H + jj;
+    for (int jj = 0; jj < HB; ++jj) {
+      const int blk = qd + 4 * jj;
       const bool isx = blk < kCrossA;
       const int c0 = isx ? a0 + 16 * blk : b0 + 16 * (blk - kCrossA);
       const int nc = isx ? a.nx : a.ny;
@@ -1154,56 +1165,84 @@ __device__ __forceinline__ void cross_pass_body(const CrossArgs& a, const int bi
       }
     }
   };
-
-  d4 acc[KP];
-  int pi[KP], pj[KP];
+  auto store = [&](int64_t t, const d4 (&w)[HB], double* buf) {
+    const bool ok = t < tiles && t * 16 + x < a.m;
+    double* my = buf + tr * NBLK * 4 * kOpSlot;
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    acc[k] = d4{0.0, 0.0, 0.0, 0.0};
-    const int pidx = wave + kGramWaves * k;
-    pi[k] = pidx / NB;
-    pj[k] = pidx - pi[k] * NB;
-  }
-  d4 wnext[H];
-  load_h(min(s0 * kWaves + tw, tiles - 1), wnext);
-  double* myop = lds + tw * NBLK * 4 * kOpSlot;
-  for (int64_t s = s0; s < s1; ++s) {
-    const int64_t t = s * kWaves + tw;
-    const bool tile_ok = t < tiles && t * 16 + x < a.m;
-#pragma unroll
-    for (int jj = 0; jj < H; ++jj) {
-      const int blk = half * H + jj;
+    for (int jj = 0; jj < HB; ++jj) {
+      const int blk = qd + 4 * jj;
       if (blk < NBLK) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          myop[(blk * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = tile_ok ? wnext[jj][r] : 0.0;
+          my[(blk * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = ok ? w[jj][r] : 0.0;
       }
     }
-    load_h(min(t + kWaves, tiles - 1), wnext);
-    __syncthreads();
+  };
+
+  d4 acc[WI][WJ];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const double* oa = lds + pi[k] * 4 * kOpSlot + x + 17 * g;
-      const double* ob = lds + (kCrossA + pj[k]) * 4 * kOpSlot + x + 17 * g;
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-      for (int u4 = 0; u4 < kWaves; ++u4)
+    for (int j = 0; j < WJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  auto tile_of = [&](int64_t s) { return min(s, s1 - 1) * 2 + tr; };
+  auto compute = [&](const double* cur) {
+    const double* oa = cur + (gi * WI) * 4 * kOpSlot + x + 17 * g;
+    const double* ob = cur + (kCrossA + gj * WJ) * 4 * kOpSlot + x + 17 * g;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          acc[k] = mfma(oa[(u4 * NBLK * 4 + u) * kOpSlot], ob[(u4 * NBLK * 4 + u) * kOpSlot], acc[k]);
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double av[WI], bv[WJ];
+#pragma unroll
+        for (int i = 0; i < WI; ++i) av[i] = oa[((tt * NBLK + i) * 4 + u) * kOpSlot];
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) bv[j] = ob[((tt * NBLK + j) * 4 + u) * kOpSlot];
+#pragma unroll
+        for (int i = 0; i < WI; ++i)
+#pragma unroll
+          for (int j = 0; j < WJ; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+      }
+  };
+  // two register sets: step k's loads land in set k % 2 two steps before it
+  // is stored (the loads have two compute phases to arrive)
+  double* buf0 = lds;
+  double* buf1 = lds + BUF;
+  d4 wa[HB], wb[HB];
+  if (s0 < s1) {
+    load(tile_of(s0), wa);
+    load(tile_of(s0 + 1), wb);
+    store(tile_of(s0), wa, buf0);
+    load(tile_of(s0 + 2), wa);
+  }
+  __syncthreads();
+  for (int64_t s = s0; s < s1; s += 2) {
+    if (s + 1 < s1) {
+      store(tile_of(s + 1), wb, buf1);
+      load(tile_of(s + 3), wb);
     }
+    compute(buf0);
+    __syncthreads();
+    if (s + 1 >= s1) break;
+    if (s + 2 < s1) {
+      store(tile_of(s + 2), wa, buf0);
+      load(tile_of(s + 4), wa);
+    }
+    compute(buf1);
     __syncthreads();
   }
   // lane (x, g) register r: B~[a0 + 16 I + g + 4r][b0 + 16 J + x]
   double* out = a.part + (int64_t)slot * a.part_stride;
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int col = b0 + 16 * pj[k] + x;
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = a0 + 16 * pi[k] + g + 4 * r;
-      if (row < a.rows16 && col < a.pitch) out[(int64_t)row * a.pitch + col] = acc[k][r];
+    for (int j = 0; j < WJ; ++j) {
+      const int col = b0 + 16 * (gj * WJ + j) + x;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = a0 + 16 * (gi * WI + i) + g + 4 * r;
+        if (row < a.rows16 && col < a.pitch) out[(int64_t)row * a.pitch + col] = acc[i][j][r];
+      }
     }
-  }
 }
 
 template <int NB>

@@ -644,7 +644,7 @@ def test_batch_rejects_wide_basis_append():
 
 
 # --------------------------------------------------------------------------
-# blocks wider than 528 columns: the apply in superblocks of 512 columns
+# blocks wider than 528 columns: the apply in superblocks of 128 columns
 # (proj_pass for the earlier superblocks), the Gramian from cross_pass, the
 # small matrices of small_step in the workspace
 # --------------------------------------------------------------------------
