@@ -1144,37 +1144,53 @@ __device__ __forceinline__ void cross_pass_body(const CrossArgs& a, const int bi
 
   // blocks qd, qd + 4, ... of row tile t: blocks 0..7 are basis columns a0..,
   // blocks 8.. block columns b0..; one descriptor per block (columns past the
-  // matrix read zero); rows past m read a clamped row and are zeroed where
-  // the tile goes into LDS
+  // matrix read zero).  The per-lane offsets ((g + 4r) ld + x) * 8 are formed
+  // once; a step adds its first row as the scalar offset, so the loads need
+  // no address arithmetic.  Rows past m read the next column's top (or zero
+  // past the last column) and are zeroed where the tile goes into LDS; every
+  // offset stays below (16 ld + 14) * 8 < 2^32.
+  __amdgpu_buffer_rsrc_t rsb[HB];
+  uint32_t vo[HB][4];
+#pragma unroll
+  for (int jj = 0; jj < HB; ++jj) {
+    const int blk = qd + 4 * jj;
+    const bool isx = blk < kCrossA;
+    const int c0 = isx ? a0 + 16 * blk : b0 + 16 * (blk - kCrossA);
+    const int nc = isx ? a.nx : a.ny;
+    const int64_t ld = isx ? a.ldx : a.ldy;
+    const int64_t nrec = (blk < NBLK && nc - 1 >= c0) ? (((int64_t)(nc - 1 - c0) * ld + a.m) * 8) : 0;
+    rsb[jj] = make_rsrc((isx ? a.x : a.y) + (int64_t)c0 * ld, nrec);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) vo[jj][r] = (uint32_t)(((int64_t)(g + 4 * r) * ld + x) * 8);
+  }
   auto load = [&](int64_t t, d4 (&w)[HB]) {
-    const int64_t row = t * 16 + x;
-    const int64_t rowc = row < a.m ? row : a.m - 1;
+    const int so = __builtin_amdgcn_readfirstlane((int)(t * 128));
 #pragma unroll
-    for (int jj = 0; jj < HB; ++jj) {
-      const int blk = qd + 4 * jj;
-      const bool isx = blk < kCrossA;
-      const int c0 = isx ? a0 + 16 * blk : b0 + 16 * (blk - kCrossA);
-      const int nc = isx ? a.nx : a.ny;
-      const int64_t ld = isx ? a.ldx : a.ldy;
-      const int64_t nrec = (blk < NBLK && nc - 1 >= c0) ? (((int64_t)(nc - 1 - c0) * ld + a.m) * 8) : 0;
-      const __amdgpu_buffer_rsrc_t rs = make_rsrc((isx ? a.x : a.y) + (int64_t)c0 * ld, nrec);
+    for (int jj = 0; jj < HB; ++jj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t o = (uint32_t)(((int64_t)(g + 4 * r) * ld + rowc) * 8);
-        w[jj][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)o, 0, 0));
-      }
-    }
+      for (int r = 0; r < 4; ++r)
+        w[jj][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsb[jj], (int)vo[jj][r], so, 0));
   };
   auto store = [&](int64_t t, const d4 (&w)[HB], double* buf) {
-    const bool ok = t < tiles && t * 16 + x < a.m;
-    double* my = buf + tr * NBLK * 4 * kOpSlot;
+    double* my = buf + tr * NBLK * 4 * kOpSlot + (x >> 2) * kOpSlot + 17 * (x & 3) + g;
+    if ((t + 1) * 16 <= a.m) {   // a whole tile of rows (uniform): no mask
 #pragma unroll
-    for (int jj = 0; jj < HB; ++jj) {
-      const int blk = qd + 4 * jj;
-      if (blk < NBLK) {
+      for (int jj = 0; jj < HB; ++jj) {
+        const int blk = qd + 4 * jj;
+        if (blk < NBLK) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          my[(blk * 4 + (x >> 2)) * kOpSlot + 17 * (x & 3) + g + 4 * r] = ok ? w[jj][r] : 0.0;
+          for (int r = 0; r < 4; ++r) my[blk * 4 * kOpSlot + 4 * r] = w[jj][r];
+        }
+      }
+    } else {
+      const bool ok = t < tiles && t * 16 + x < a.m;
+#pragma unroll
+      for (int jj = 0; jj < HB; ++jj) {
+        const int blk = qd + 4 * jj;
+        if (blk < NBLK) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) my[blk * 4 * kOpSlot + 4 * r] = ok ? w[jj][r] : 0.0;
+        }
       }
     }
   };
