@@ -585,7 +585,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
     a.p = cols; a.m = m;
     a.tiles_b = (int)((nblocks(cols) + nb8 - 1) / nb8);
     a.done = &b->ctrl->done;
-    L.grid = ((m + 127) / 128) * a.tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
+    L.grid = ((m + kProjRows - 1) / kProjRows) * a.tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
     record(L);
     out.push_back(L);
   };
@@ -891,7 +891,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       a.bt = b->stage_bt; a.ldt = pitch; a.rows16 = rows16;
       a.p = (int)c.p; a.m = b->m; a.tiles_b = tiles_b;
       a.done = &b->ctrl->done;
-      L.grid = ((b->m + 127) / 128) * tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
+      L.grid = ((b->m + kProjRows - 1) / kProjRows) * tiles_b; L.threads = kThreads; L.lds = 8 * (size_t)proj_lds_doubles(nb8);
       L.prof_kind = 1; L.prof_bytes = pass_bytes; L.prof_join = false;
       out.push_back(L);
     }

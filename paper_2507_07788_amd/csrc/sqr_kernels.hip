@@ -1266,13 +1266,16 @@ __global__ __launch_bounds__(kGramThreads) void cross_pass(CrossArgs a) {
   cross_pass_body<NB>(a, blockIdx.x);
 }
 
-// Z = W - X B~ for 128 rows (32 per wave, two 16-row tiles) x 16 NB columns.
+// Z = W - X B~ for kProjRows rows (kProjRT 16-row tiles per wave) x 16 NB
+// columns.
 // B~ streams through LDS in chunks of kProjKC rows (double-buffered, one
 // barrier per chunk); the basis operand is loaded straight into registers,
 // one chunk ahead.  MFMA roles: A = B~ slice (from LDS), B = X rows, so the
 // result lane (x, g) register r is Z[row x][column g + 4r] (stores coalesce
 // along rows).
 constexpr int kProjKC = 32;
+constexpr int kProjRT = 1;                     // 16-row tiles per wave
+constexpr int kProjRows = 16 * kProjRT * kWaves;   // rows per workgroup
 __host__ __device__ constexpr int proj_pitch(int nb) { return 32 * ((16 * nb + 31) / 32) + 16; }
 __host__ __device__ constexpr int proj_lds_doubles(int nb) { return 2 * kProjKC * proj_pitch(nb); }
 
@@ -1288,20 +1291,20 @@ __device__ __forceinline__ void proj_pass_body(const ProjArgs& a, const int bid)
   const int x = lane & 15, g = lane >> 4;
   const int rt = bid / a.tiles_b, tb = bid - rt * a.tiles_b;
   const int b0 = 16 * NB * tb;
-  const int64_t rbase = (int64_t)rt * 128 + wave * 32;
+  const int64_t rbase = (int64_t)rt * kProjRows + wave * 16 * kProjRT;
   const int nch = (a.rows16 + kProjKC - 1) / kProjKC;
-  int64_t rowc[2];
+  int64_t rowc[kProjRT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) rowc[t] = min(rbase + 16 * t + x, a.m - 1);
+  for (int t = 0; t < kProjRT; ++t) rowc[t] = min(rbase + 16 * t + x, a.m - 1);
 
   // basis operand of chunk ch: lane (x, g), tile t, slice s holds
   // X[row][k0 + 4s + g] (column clamped; zeroed at use past nx)
-  auto load_x = [&](int ch, double (&xv)[2][SL]) {
+  auto load_x = [&](int ch, double (&xv)[kProjRT][SL]) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const int k = min(ch * kProjKC + 4 * s + g, a.nx - 1);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) xv[t][s] = a.x[(int64_t)k * a.ldx + rowc[t]];
+      for (int t = 0; t < kProjRT; ++t) xv[t][s] = a.x[(int64_t)k * a.ldx + rowc[t]];
     }
   };
   // B~ chunk: thread -> row (tid >> 3) of the chunk, columns (tid & 7) * PER ..
@@ -1318,28 +1321,30 @@ __device__ __forceinline__ void proj_pass_body(const ProjArgs& a, const int bid)
     for (int e = 0; e < PER; ++e)
       buf[brow * LP + bcol + e] = (rok && b0 + bcol + e < a.p) ? bv[e] : 0.0;
   };
-  d4 acc[2][NB];
+  d4 acc[kProjRT][NB];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < kProjRT; ++t)
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
-  auto compute = [&](int ch, const double (&xv)[2][SL], const double* buf) {
+  auto compute = [&](int ch, const double (&xv)[kProjRT][SL], const double* buf) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const bool kok = ch * kProjKC + 4 * s + g < a.nx;
-      const double x0 = kok ? xv[0][s] : 0.0, x1 = kok ? xv[1][s] : 0.0;
+      double xk[kProjRT];
+#pragma unroll
+      for (int t = 0; t < kProjRT; ++t) xk[t] = kok ? xv[t][s] : 0.0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const double bv = buf[(4 * s + g) * LP + 16 * c + x];
-        acc[0][c] = mfma(bv, x0, acc[0][c]);
-        acc[1][c] = mfma(bv, x1, acc[1][c]);
+#pragma unroll
+        for (int t = 0; t < kProjRT; ++t) acc[t][c] = mfma(bv, xk[t], acc[t][c]);
       }
     }
   };
 
   double* buf0 = lds;
   double* buf1 = lds + kProjKC * LP;
-  double xa[2][SL], xb[2][SL];
+  double xa[kProjRT][SL], xb[kProjRT][SL];
   double bv[PER];
   load_x(0, xa);
   load_b(0, bv);
@@ -1357,7 +1362,7 @@ __device__ __forceinline__ void proj_pass_body(const ProjArgs& a, const int bid)
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < kProjRT; ++t) {
     const int64_t row = rbase + 16 * t + x;
     if (row >= a.m) continue;
 #pragma unroll
