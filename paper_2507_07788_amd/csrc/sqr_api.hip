@@ -190,6 +190,7 @@ struct sqr_basis {
   int slots_g = 0;
   int64_t pbig = 0;
   double *partg = nullptr, *stage_g = nullptr, *rt = nullptr, *vec = nullptr;
+  double* errpart = nullptr;         // xfill_pass: one partial sum per tile
 };
 
 namespace {
@@ -374,7 +375,7 @@ void set_kernel_attributes() { std::call_once(g_attr_once, set_kernel_attributes
 // Sizes (doubles) of the workspace regions of a handle.  bt, pp and slots_c
 // serve appends with a wide basis; g, rt, vec and slots_g blocks wider than
 // kMaxSCols (zero where the handle never takes that route).
-struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp, g, rt, vec; int slots_c, slots_g; };
+struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp, g, rt, vec, errp; int slots_c, slots_g; };
 
 // Every call with a block of up to kMaxSCols columns a handle of capacity
 // cap can make (q + p <= cap): on block_pass the sizes grow with q, so the
@@ -382,7 +383,7 @@ struct WsSizes { int64_t tl, arena, bneg, rinv, bt, pp, g, rt, vec; int slots_c,
 // block regions for q = 0 (covered) and B~ for the widest basis.  Blocks
 // on the wide-block route are covered up to pbig columns (0: none).
 WsSizes handle_sizes(int64_t cap, int64_t pbig) {
-  WsSizes z{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  WsSizes z{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t pmax = std::min<int64_t>(cap, kMaxSCols);
   for (int64_t p = 1; p <= pmax; ++p) {
     const int64_t q1 = std::min(cap - p, q_fit(p));
@@ -407,6 +408,7 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
     z.g = p16 * p16;
     z.rt = p * p;
     z.vec = p > kMaxCols ? 2 * p : 0;
+    z.errp = ((p + 31) / 32) * ((p + 31) / 32);   // xfill_pass partial sums
     z.pp = std::max(z.pp, p * p);   // R_old (and B~^T B~ with a basis)
     if (cap - p > 0) {
       // any block of more than kMaxSCols columns with a basis beside it
@@ -422,7 +424,7 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
 
 // One orthogonalisation of n <= kMaxSCols columns (no later appends).
 WsSizes orth_sizes(int64_t n) {
-  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0, 0, 0, 0, 0};
+  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0, 0, 0, 0, 0, 0};
 }
 
 // Partial-Gram slots for m rows: one per resident workgroup at most, within
@@ -454,6 +456,7 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
   const size_t o_g = big ? take(z.g) : 0;
   const size_t o_rt = big ? take(z.rt) : 0;
   const size_t o_vec = z.vec ? take(z.vec) : 0;
+  const size_t o_errp = z.errp ? take(z.errp) : 0;
   if (base) {
     b->slots = slots;
     b->part = base + o_part; b->stage = base + o_stage;
@@ -470,6 +473,7 @@ size_t carve_workspace(sqr_basis* b, double* base, const WsSizes& z, int slots) 
     b->stage_g = big ? base + o_g : nullptr;
     b->rt = big ? base + o_rt : nullptr;
     b->vec = z.vec ? base + o_vec : nullptr;
+    b->errpart = z.errp ? base + o_errp : nullptr;
   }
   return doubles;
 }
@@ -709,6 +713,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
   k.shift_policy = b->opts.shift_policy; k.shift_dim = b->opts.append_shift_dim;
   k.mixed = 0;
   k.lds_matrices = 0;   // the small matrices of a wide block live in the workspace
+  k.errpart = b->errpart; k.nerr = (int)(((c.p + 31) / 32) * ((c.p + 31) / 32));   // X from xfill_pass
   auto small = [&](int stage) {
     Launch L;
     memset(&L, 0, sizeof(L));
@@ -724,6 +729,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
   g.X = b->X; g.M = b->X + (int64_t)c.p * c.p; g.p = (int)c.p; g.ctrl = b->ctrl;
   g.rinv = b->rinv; g.rold = b->rold; g.R = b->R; g.ldr = b->ldr; g.q = (int)c.q; g.phase = phase;
   g.rt = b->rt; g.bneg = b->bneg;
+  g.E = b->stage_g; g.btb = basis ? b->btb : nullptr; g.errpart = b->errpart;
   auto big = [&](const void* kern, int64_t grid, int threads, int k0) {
     Launch L;
     memset(&L, 0, sizeof(L));
@@ -734,8 +740,9 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
     L.prof_kind = -1;
     out.push_back(L);
   };
-  small(1);
   const int64_t tp = (c.p + 31) / 32;
+  big((const void*)xfill_pass, tp * tp, kThreads, 0);
+  small(1);
   big((const void*)mfill_pass, tp * tp, kThreads, 0);
   for (int64_t k0 = 0; k0 < c.p; k0 += kBand) {
     const int64_t k1 = std::min<int64_t>(c.p, k0 + kBand);
@@ -1659,7 +1666,7 @@ int sqr_park(sqr_basis* b) {
   b->ws = nullptr; b->ws_bytes = 0; b->ctrl_host = nullptr; b->ctrl_host_dev = nullptr;
   b->ctrl = nullptr; b->part = b->stage = b->X = b->bneg = b->rinv = nullptr;
   b->partc = b->stage_bt = b->btb = b->rold = nullptr;
-  b->partg = b->stage_g = b->rt = b->vec = nullptr;
+  b->partg = b->stage_g = b->rt = b->vec = b->errpart = nullptr;
   b->pbig = 0;
   return SQR_OK;
 }

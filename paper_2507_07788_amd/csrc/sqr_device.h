@@ -133,7 +133,7 @@ struct BaccArgs {
 // The kernels around small_step for blocks wider than kMaxSCols (p x p
 // row-major matrices in the workspace).
 struct BigArgs {
-  const double* X;        // the Schur complement (symmetric)
+  double* X;              // the Schur complement (symmetric)
   double* M;              // X + sigma I, then its upper Cholesky factor
   int32_t p;
   int32_t k0;             // chol_*: first row of the band
@@ -143,6 +143,12 @@ struct BigArgs {
   double* R; int64_t ldr; int32_t q; int32_t phase;
   double* rt;             // R~ row-major, zero below the diagonal
   double* bneg;           // C_J per superblock
+  // xfill_pass: X = G - B~^T B~ from the reduced Gramian E (row-major, pitch
+  // p rounded up to 16, upper tiles valid) and btb (appends), and one partial
+  // sum of squares of X - I per workgroup
+  const double* E;
+  const double* btb;      // NULL without a basis
+  double* errpart;
 };
 
 // Argument table of a batched launch: call c owns workgroups start[c] ..
@@ -197,6 +203,10 @@ struct SmallArgs {
   double* rold;
   double* rt;
   double* vec;           // 2 p doubles for blocks wider than kMaxCols
+  // ext bit 1: X already formed by xfill_pass, with nerr partial sums of
+  // squares of X - I (0: this kernel forms X)
+  const double* errpart;
+  int32_t nerr;
 };
 
 }  // namespace sqr

@@ -1866,7 +1866,8 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   const double* E = a.E;
   const int64_t epitch = (p + 15) & ~15;
   const bool ph0 = a.phase == 0;
-  if (front) {
+  const bool xpre = a.nerr > 0;   // X formed by xfill_pass
+  if (front && !xpre) {
     // 1. Gramian blocks from the reduced slots: B~ = E[0:q, :],
     //    G = E[q:q+p, :] (upper, mirrored).
     fill_rows(X, p, p, [&](int i, int j) {
@@ -2163,13 +2164,15 @@ __device__ __forceinline__ void small_step_body(const SmallArgs& a) {
   };
   // 3. ||X - I||_F (the second stage reads the first stage's value).
   double part = 0.0;
-  for (int i = front ? (tid >> 4) : p; i < p; i += kSmallThreads / 16) {
+  for (int i = (front && !xpre) ? (tid >> 4) : p; i < p; i += kSmallThreads / 16) {
 #pragma unroll 4
     for (int j = tid & 15; j < p; j += 16) {
       const double d = X[(int64_t)i * p + j] - (i == j ? 1.0 : 0.0);
       part += d * d;
     }
   }
+  if (front && xpre)   // xfill_pass's partial sums, added in a fixed order
+    for (int i = tid; i < a.nerr; i += kSmallThreads) part += a.errpart[i];
   const double err = front ? sqrt(block_sum(part, red, lo)) : c->orth_fro;
   // Shift policy of an orth call (appends always follow Algorithm 2):
   // 0 Algorithm 1 (recomputed from the current X, x10 escalation), 1 none
@@ -2478,6 +2481,49 @@ __global__ __launch_bounds__(kSmallThreads) void small_step_batch(BatchTable<Sma
 // trmm_pass forms R <- R~ R_old and cj_pass the C_J and R~ of the next pass.
 // ---------------------------------------------------------------------------
 constexpr int kBand = 64;
+
+// X = G - B~^T B~ (both triangles, from the upper tiles of the reduced
+// Gramian) in 32 x 32 tiles, and the tile's sum of squares of X - I (lanes,
+// then waves in order) into errpart[tile].
+__global__ __launch_bounds__(kThreads) void xfill_pass(BigArgs a) {
+  __shared__ double L[32][33];
+  __shared__ double red[kWaves];
+  if (a.phase > 0 && a.ctrl->done) return;
+  const int p = a.p;
+  const int64_t pitch = (p + 15) & ~15;
+  const int tp = (p + 31) / 32;
+  const int ti = (int)blockIdx.x / tp, tj = (int)blockIdx.x % tp;
+  const int lo = min(ti, tj), hi = max(ti, tj);
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ly; r < 32; r += 8) {
+    const int i = 32 * lo + r, j = 32 * hi + lx;
+    L[r][lx] = (i < p && j < p) ? a.E[(int64_t)i * pitch + j] : 0.0;
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int r = ly; r < 32; r += 8) {
+    const int i = 32 * ti + r, j = 32 * tj + lx;
+    if (i >= p || j >= p) continue;
+    double g;
+    if (ti < tj) g = L[r][lx];
+    else if (ti > tj) g = L[lx][r];
+    else g = L[min(r, lx)][max(r, lx)];
+    const double xv = g - (a.btb ? a.btb[(int64_t)i * p + j] : 0.0);
+    a.X[(int64_t)i * p + j] = xv;
+    const double d = xv - (i == j ? 1.0 : 0.0);
+    part += d * d;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+    a.errpart[blockIdx.x] = s;
+  }
+}
 
 // M = X + sigma I and rold = R_old (row-major; the identity at phase 0),
 // 32 x 32 tiles (R_old is read along its columns and written along rows).
