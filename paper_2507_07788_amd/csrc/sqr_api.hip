@@ -200,18 +200,27 @@ typedef void (*BlockBatchKernel)(BatchTable<BlockPassArgs>);
 // nt = S tiles per wave, wpt = waves sharing a row tile (4 / wpt row tiles
 // in flight per workgroup); a variant covers nt * wpt tiles of S.  Every
 // kernel comes with its batched form (the same work for several calls in one
-// launch).
+// launch).  The Gram-only pass takes two waves per row tile up to 12 tiles of
+// S (two row tiles in flight per workgroup; measured 7 % faster than four
+// waves per tile on the growth workload), the apply four from 5 tiles on (its
+// members' partial Y meet at a barrier every step; fewer, wider members
+// measured slower).  Variants that serve only the Gram-only pass have no
+// apply kernel.
 struct Variant { int nt, wpt; BlockKernel gram, apply; BlockBatchKernel gram_b, apply_b; };
 int g_occ[2][32];     // workgroups per CU of each variant (gram, apply)
 int g_ncu = 0;
 #define SQR_VARIANT(NT, W) {NT, W, block_pass<NT, W, false>, block_pass<NT, W, true>, \
                             block_pass_batch<NT, W, false>, block_pass_batch<NT, W, true>}
+#define SQR_GVARIANT(NT, W) {NT, W, block_pass<NT, W, false>, nullptr, \
+                             block_pass_batch<NT, W, false>, nullptr}
 const Variant kVariants[] = {
   SQR_VARIANT(1, 1), SQR_VARIANT(1, 2), SQR_VARIANT(2, 2),
+  SQR_GVARIANT(3, 2), SQR_GVARIANT(4, 2), SQR_GVARIANT(5, 2), SQR_GVARIANT(6, 2),
   SQR_VARIANT(2, 4), SQR_VARIANT(3, 4), SQR_VARIANT(4, 4), SQR_VARIANT(5, 4),
   SQR_VARIANT(6, 4), SQR_VARIANT(7, 4), SQR_VARIANT(8, 4), SQR_VARIANT(9, 4),
 };
 #undef SQR_VARIANT
+#undef SQR_GVARIANT
 
 // Whole-pass kernels of orth calls with up to 8 column blocks (FP64 calls use
 // them from 2 blocks on; the mixed form from 1), with FP64 or FP32 Gramians.
@@ -260,19 +269,25 @@ size_t wide_lds_bytes(int nb, bool apply) {
   return 8 * ((size_t)(apply ? wide_panel_doubles(nb) : 0) + (size_t)wide_op_doubles(nb));
 }
 
-// Smallest variant whose S capacity covers ns tiles (listed by capacity).
-const Variant* pick_variant(int ns) {
-  for (const Variant& v : kVariants)
+// Smallest variant of the pass kind whose S capacity covers ns tiles (each
+// kind's variants are listed by capacity).
+const Variant* pick_variant(int ns, bool apply) {
+  for (const Variant& v : kVariants) {
+    if (apply ? !v.apply : (v.wpt == 4 && v.nt <= 3)) continue;
     if (v.nt * v.wpt >= std::max(ns, 1)) return &v;
+  }
   return nullptr;
 }
 
 size_t block_lds_bytes(const Variant& v, bool apply) {
-  // main loop: partial T tiles + transposition tiles (the final cross-group
-  // reduction, at most 4 groups x 2 tiles or 2 groups x 5 tiles, fits in
-  // them); the apply adds its operands C_J (16 nt wpt rows) and D_J
-  return 8 * ((size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch +
-              (apply ? (size_t)v.nt * v.wpt * 256 + 256 : 0));
+  // main loop: partial T tiles + transposition tiles; the apply adds its
+  // operands C_J (16 nt wpt rows) and D_J.  The final cross-group reduction
+  // (groups x (nt wpt + 1) tiles) reuses the area from its start.
+  const size_t groups = kWaves / v.wpt;
+  const size_t red = groups > 1 ? groups * (size_t)(v.nt * v.wpt + 1) * kTPart : 0;
+  const size_t loop = (size_t)2 * kWaves * kTPart + (size_t)kWaves * 16 * kYPitch +
+                      (apply ? (size_t)v.nt * v.wpt * 256 + 256 : 0);
+  return 8 * std::max(loop, red);
 }
 
 // Kernel attributes and occupancies, once per process (std::call_once: the
@@ -284,9 +299,11 @@ void set_kernel_attributes_once() {
   };
   for (const Variant& v : kVariants) {
     lds_attr((const void*)v.gram, 120 * 1024);
-    lds_attr((const void*)v.apply, 120 * 1024);
     lds_attr((const void*)v.gram_b, 120 * 1024);
-    lds_attr((const void*)v.apply_b, 120 * 1024);
+    if (v.apply) {
+      lds_attr((const void*)v.apply, 120 * 1024);
+      lds_attr((const void*)v.apply_b, 120 * 1024);
+    }
   }
   if (hipFuncSetAttribute((const void*)small_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kSmallLdsBytes) != hipSuccess ||
@@ -324,6 +341,10 @@ void set_kernel_attributes_once() {
   for (const Variant& v : kVariants) {
     for (int ap = 0; ap < 2; ++ap) {
       int n = 1;
+      if (ap && !v.apply) {   // a Gram-only variant
+        g_occ[ap][i] = 1;
+        continue;
+      }
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)(ap ? v.apply : v.gram),
                                                         kThreads, block_lds_bytes(v, ap != 0)) != hipSuccess ||
           n < 1)
@@ -607,7 +628,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
              c.y, c.ldy, (int)k0, b->rt + k0, c.p, (int)k0, (int)w);
       int64_t nwg = b->slots;
       for (int64_t J = 0; J < PK; ++J) {
-        const Variant* v = pick_variant((int)J);
+        const Variant* v = pick_variant((int)J, true);
         nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_occ[1][variant_index(v)]);
         nwg = std::min<int64_t>(nwg, (tiles + (kWaves / v->wpt) - 1) / (kWaves / v->wpt));
       }
@@ -632,7 +653,7 @@ int plan_big(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) {
         a.done = &b->ctrl->done;
         a.passes = &b->ctrl->passes;
         a.copy_if_done = 0;
-        const Variant* v = pick_variant((int)Jl);
+        const Variant* v = pick_variant((int)Jl, true);
         L.kind = Launch::kBlock;
         L.k1 = (const void*)v->apply; L.kb = (const void*)v->apply_b;
         L.grid = nwg; L.threads = kThreads; L.lds = block_lds_bytes(*v, true);
@@ -907,7 +928,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     // capped by the slot capacity and by the row tiles available.
     for (int64_t J = 0; J < P; ++J) {
       const int ks = (int)round16(qb) + (int)(16 * J);
-      const Variant* v = pick_variant((ks + 15) / 16);
+      const Variant* v = pick_variant((ks + 15) / 16, apply);
       if (!v) return SQR_EDIM;
       const int occ = g_occ[apply ? 1 : 0][variant_index(v)];
       nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * occ);
@@ -936,7 +957,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
       a.passes = &b->ctrl->passes;
       a.copy_if_done = (phase == 1) && !wideb;
       const int ks = (int)round16(a.n1) + a.n2;   // columns of S with the padding
-      const Variant* v = pick_variant((ks + 15) / 16);
+      const Variant* v = pick_variant((ks + 15) / 16, apply);
       L.kind = Launch::kBlock;
       L.k1 = (const void*)(apply ? v->apply : v->gram);
       L.kb = (const void*)(apply ? v->apply_b : v->gram_b);

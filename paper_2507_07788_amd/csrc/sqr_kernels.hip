@@ -69,6 +69,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// The LDS instructions of one wave are performed in the order they are
+// issued, so a wave-private exchange (lanes write, then read what other lanes
+// of the same wave wrote) needs no wait for the writes to complete: only the
+// compiler must keep the order of the accesses.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Batched launches: the workgroups of call c are start[c] .. start[c+1]-1 of
 // the grid; each reads its call's argument block from the table.
@@ -105,7 +114,7 @@ constexpr int kTPart = 256;    // doubles per 16x16 tile in LDS
 
 // Waves per SIMD the register allocation must leave room for: three for the
 // variants up to 12 S tiles (their LDS allows three workgroups per CU), one
-// for the wider ones.
+// for the wider ones, two for the Gram-only pairs of 3..6 tiles per wave.
 template <int NTW, int WPT, bool APPLY>
 __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const int bid, const int nwg) {
   // LDS: double-buffered partial T tiles (2 x 4 x 256 doubles), then one
@@ -120,16 +129,18 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
   const int x = lane & 15;
   const int g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
-  const int64_t per = (tiles + nwg - 1) / nwg;   // row tiles per workgroup
-  const int64_t t0 = (int64_t)bid * per;
-  const int64_t t1 = min(tiles, t0 + per);
+  // The row tiles are dealt out round-robin: local tile i of this workgroup
+  // is row tile i nwg + bid, so the workgroups of the grid stream one band of
+  // rows together.
+  const int64_t tw = tiles > bid ? (tiles - 1 - bid) / nwg + 1 : 0;
+  auto tile_of = [&](int64_t i) { return i * nwg + bid; };
 
   if (a.done && *a.done) {
     // A finished call: nothing to do, except that the first apply of a call
     // that converged before any pass copies the input block to the output.
     if (APPLY && a.copy_if_done && *a.passes == 0) {
-      for (int64_t t = t0 + wave; t < t1; t += kWaves) {
-        const int64_t row = t * 16 + x;
+      for (int64_t i = wave; i < tw; i += kWaves) {
+        const int64_t row = tile_of(i) * 16 + x;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = g + 4 * r;
@@ -166,12 +177,12 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
   for (int j = 0; j < NTW; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   d4 accg = d4{0.0, 0.0, 0.0, 0.0};
 
-  // Step k of a group handles row tile t0 + k G + grp.  The member that owns
+  // Step k of a group handles local tile k G + grp.  The member that owns
   // step k (k mod WPT) adds W_J D_J to the apply, stores Y and accumulates
   // Y^T Y, so this extra work rotates over the members (and their SIMDs).
   // In the apply only the owner needs the block input; in the Gram-only pass
   // every member does (Y = W).
-  const int nsteps = (int)((t1 - t0 + G - 1) / G);   // the same for every wave
+  const int nsteps = (int)((tw + G - 1) / G);   // the same for every wave
   // Loads of one step: my S slices and (if needed) the block input.  One
   // buffer descriptor per 16-column tile: base at the tile's first column,
   // range = bytes up to the end of its segment's last column, so columns past
@@ -182,9 +193,9 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
   // not here, so the loads stay in flight until then.
   const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win, ((int64_t)(a.pb - 1) * a.ldw + a.m) * 8);
   auto load_step = [&](int k, double (&sreg)[NTW][4], d4& w, uint64_t& keep) {
-    const int64_t tile = t0 + (int64_t)k * G + grp;
-    const int64_t row = min(tile, t1 - 1) * 16 + x;
-    keep = (tile < t1 && row < a.m) ? ~0ull : 0ull;
+    const int64_t li = (int64_t)k * G + grp;
+    const int64_t row = tile_of(min(li, max(tw - 1, (int64_t)0))) * 16 + x;
+    keep = (li < tw && row < a.m) ? ~0ull : 0ull;
     const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
@@ -217,8 +228,9 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
   };
 
   auto do_step = [&](int k, const double (&sreg)[NTW][4], const d4& wraw, uint64_t keep) {
-    const int64_t tile = t0 + (int64_t)k * G + grp;
-    const bool tile_ok = tile < t1;
+    const int64_t li = (int64_t)k * G + grp;
+    const bool tile_ok = li < tw;
+    const int64_t tile = tile_of(li);
     const int64_t row = tile * 16 + x;
     const bool row_ok = keep != 0;
     const bool own = k % WPT == mem;     // wave-uniform
@@ -276,11 +288,11 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
     // (k-slot g of slice u <-> row g + 4u).
 #pragma unroll
     for (int r = 0; r < 4; ++r) tr[x * kYPitch + g + 4 * r] = y[r];
-    wave_lds_sync();
+    wave_lds_order();
     double yb[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) yb[u] = tr[(g + 4 * u) * kYPitch + x];
-    wave_lds_sync();
+    wave_lds_order();
     if (own) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) accg = mfma(yb[u], yb[u], accg);
@@ -291,11 +303,11 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
       if (mem + WPT * j >= ns) continue;   // no such tile of S
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) tr[x * kYPitch + 4 * jj + g] = sreg[j][jj];
-      wave_lds_sync();
+      wave_lds_order();
       double sa[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) sa[u] = tr[(g + 4 * u) * kYPitch + x];
-      wave_lds_sync();
+      wave_lds_order();
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[j] = mfma(sa[u], yb[u], acc[j]);
     }
@@ -379,12 +391,12 @@ __device__ __forceinline__ void block_pass_body(const BlockPassArgs& a, const in
 }
 
 template <int NTW, int WPT, bool APPLY>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPT == 2 && NTW >= 3 ? 2 : (NTW * WPT <= 12 ? 3 : 1))))
 void block_pass(BlockPassArgs a) {
   block_pass_body<NTW, WPT, APPLY>(a, blockIdx.x, gridDim.x);
 }
 template <int NTW, int WPT, bool APPLY>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NTW * WPT <= 12 ? 3 : 1)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPT == 2 && NTW >= 3 ? 2 : (NTW * WPT <= 12 ? 3 : 1))))
 void block_pass_batch(BatchTable<BlockPassArgs> t) {
   const int c = batch_call(t);
   block_pass_body<NTW, WPT, APPLY>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
