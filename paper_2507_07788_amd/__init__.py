@@ -130,8 +130,12 @@ def _ld(t: torch.Tensor) -> int:
 
 
 def _stream(stream) -> int:
-    s = torch.cuda.current_stream() if stream is None else stream
-    return s.cuda_stream
+    if stream is not None:
+        return stream.cuda_stream
+    # the raw handle of the current device's current stream (what
+    # torch.cuda.current_stream().cuda_stream returns, without building a
+    # Stream object on every call)
+    return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
 
 
 class Basis:

@@ -63,8 +63,11 @@ std::atomic<int64_t> g_call_id{0};
 // Caller holds g_prof_mu.
 hipEvent_t take_event() {
   if (g_event_pool.empty()) {
+    // timing only: no system-scope fence (cache writeback) at the record,
+    // which would otherwise stall the stream between the measured kernels;
+    // the records are read after the stream has been synchronised
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
   }
   hipEvent_t e = g_event_pool.back();
