@@ -419,7 +419,7 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
       z.pp = std::max(z.pp, p * p);
     }
   }
-  z.rinv = nblocks(pmax) * 256;
+  z.rinv = std::max<int64_t>(nblocks(pmax), kNarrowSlots) * 256;
   pbig = std::min(pbig, cap);
   if (pbig > 0) {
     // superblocks on block_pass, the Gramian from cross_pass, the small
@@ -448,7 +448,8 @@ WsSizes handle_sizes(int64_t cap, int64_t pbig) {
 
 // One orthogonalisation of n <= kMaxSCols columns (no later appends).
 WsSizes orth_sizes(int64_t n) {
-  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n), nblocks(n) * 256, 0, 0, 0, 0, 0, 0, 0, 0};
+  return WsSizes{total_len(0, n), small_arena(0, (int)n), bneg_len(0, n),
+                 std::max<int64_t>(nblocks(n), kNarrowSlots) * 256, 0, 0, 0, 0, 0, 0, 0, 0};
 }
 
 // Partial-Gram slots for m rows: one per resident workgroup at most, within
@@ -540,6 +541,18 @@ struct Call {
 };
 
 int variant_index(const Variant* v) { return (int)(v - kVariants); }
+
+// FP64 orthogonalisations of one block (at most 16 columns) run whole passes
+// in narrow_pass.
+bool narrow_route(const Call& c, int64_t P, bool mixed) { return c.mode == 0 && P == 1 && !mixed; }
+// The first pass that can end the call (and so writes its result): the stop
+// test runs from pass min_passes on, the last pass is max_iter; at most
+// kNarrowSlots - 1, the passes whose input is recomputed from A.
+int narrow_depth(const sqr_opts& o) {
+  return std::max(1, std::min({std::max(o.min_passes, 1), kNarrowSlots - 1, o.max_iter}));
+}
+// Slot of the inverse factor used by pass k (k >= 1).
+int narrow_slot(int k) { return std::min(k - 1, kNarrowSlots - 1); }
 
 // One kernel launch of a pass, with its single-call and batched kernels.
 struct Launch {
@@ -857,17 +870,26 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     if (!(mixed && phase == 0))
       push_wide((const void*)sv.gram, (const void*)sv.gram_b, w, nwg, kGramThreads, split_lds_bytes((int)P, false),
                 0, gb, mixed);
-  } else if (c.mode == 0 && P == 1 && !mixed) {
-    // one block: the whole pass in one launch, every wave on its own tiles
+  } else if (narrow_route(c, P, mixed)) {
+    // one block: the whole pass in one launch, every wave on its own tiles.
+    // Passes up to S = narrow_depth recompute their input from A through the
+    // inverse factors of the passes before (the same products in the same
+    // order as reading the stored result, so the same values), and only
+    // passes from S on, the ones that can end the call, write their result:
+    // CholQR3 moves 5 m n words instead of 7 m n.
     nwg = std::min<int64_t>(nwg, (int64_t)g_ncu * g_narrow_occ[apply ? 1 : 0]);
     nwg = std::max<int64_t>(1, std::min<int64_t>(nwg, (tiles + kWaves - 1) / kWaves));
+    const int S = narrow_depth(b->opts);
+    const bool from_a = !apply || phase <= S;
     WidePassArgs w;
     memset(&w, 0, sizeof(w));
-    w.win = (apply && phase > 1) ? c.y : c.win;
-    w.ldw = (apply && phase > 1) ? c.ldy : c.ldw;
+    w.win = from_a ? c.win : c.y;
+    w.ldw = from_a ? c.ldw : c.ldy;
     w.yout = c.y; w.ldy = c.ldy;
     w.n = (int)c.p; w.m = b->m;
-    w.rinv = b->rinv;
+    w.rinv = b->rinv + 256 * (from_a ? 0 : narrow_slot(phase));
+    w.levels = apply ? (from_a ? phase : 1) : 0;
+    w.store = apply && phase >= S;
     w.part = b->part; w.part_stride = tl;
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
@@ -1046,6 +1068,8 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     k.R = b->R; k.ldr = b->ldr;
     k.X = b->X;
     k.bneg = b->bneg; k.rinv = b->rinv; k.ctrl = b->ctrl;
+    // one-block orthogonalisation: the factor for pass phase + 1 goes to its slot
+    if (narrow_route(c, P, mixed)) k.rinv = b->rinv + 256 * narrow_slot(phase + 1);
     k.hctrl = b->ctrl_host_dev; k.stamp_base = b->call_id * 256; k.publish_from = b->publish_from;
     k.first_pass_shift = b->opts.first_pass_shift; k.min_passes = b->opts.min_passes;
     k.max_iter = b->opts.max_iter; k.max_escalations = b->opts.max_escalations;

@@ -67,7 +67,17 @@ struct WidePassArgs {
   // mixed form: the launch runs only if *gram32 equals the variant's Gramian
   // precision (1 = FP32); NULL: it always runs
   const int32_t* gram32;
+  // narrow_pass apply: the input is multiplied by `levels` inverse factors in
+  // turn (rinv + 256 l, l = 0 .. levels - 1), so a pass can recompute its
+  // input from A instead of reading the previous pass's result; `store`
+  // writes the result (passes that cannot end the call skip it)
+  int32_t levels, store;
 };
+
+// Slots of inverse factors kept by the one-block orthogonalisation: the
+// factor used by pass k is in slot min(k - 1, kNarrowSlots - 1), and passes
+// up to kNarrowSlots - 1 recompute their input from A through slots 0 .. k-1.
+constexpr int kNarrowSlots = 4;
 
 // One launch of reduce_slots: sum nslots partial slots (stride doubles apart)
 // of len doubles each into out, in a fixed order.

@@ -492,10 +492,19 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
     return;
   }
 
-  double dv[4];
+  // The apply multiplies the input by the inverse factors of `levels`
+  // passes in turn (a pass that recomputes its input from A); dv is the last
+  // one (the identity in the Gram-only pass, which only transposes), dp[l]
+  // the earlier ones.  k-slice s of a factor is read as D[4s + g][x].
+  const int lv = APPLY ? a.levels : 1;   // 1 .. kNarrowSlots - 1
+  double dv[4], dp[kNarrowSlots - 2][4];
 #pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4)
-    dv[s4] = APPLY ? a.rinv[(4 * s4 + g) * 16 + x] : ((4 * s4 + g == x) ? 1.0 : 0.0);
+  for (int s4 = 0; s4 < 4; ++s4) {
+    dv[s4] = APPLY ? a.rinv[(lv - 1) * 256 + (4 * s4 + g) * 16 + x] : ((4 * s4 + g == x) ? 1.0 : 0.0);
+#pragma unroll
+    for (int l = 0; l < kNarrowSlots - 2; ++l)
+      dp[l][s4] = (APPLY && l + 1 < lv) ? a.rinv[l * 256 + (4 * s4 + g) * 16 + x] : 0.0;
+  }
 
   // W tile: reg r = W[row x][col g + 4r] as loaded; columns past n read
   // zero (buffer range).  Rows past m and tiles past the range (t1) are
@@ -540,11 +549,25 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
         d4 w;
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[r] = masked(wb[q][r], kb[q]);
+        if (APPLY) {
+          // earlier passes' factors: w <- w D_l, kept in the load layout
+          // (register r = column 4r + g of row x), the products a pass that
+          // reads the stored result of the pass before would take
+#pragma unroll
+          for (int l = 0; l < kNarrowSlots - 2; ++l) {
+            if (l + 1 < lv) {   // uniform
+              d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) t = mfma(dp[l][s4], w[s4], t);
+              w = t;
+            }
+          }
+        }
         {
           d4 ya = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4) ya = mfma(w[s4], dv[s4], ya);
-          if (APPLY) {
+          if (APPLY && a.store) {
             d4 yb = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) yb = mfma(dv[s4], w[s4], yb);
