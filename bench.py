@@ -54,6 +54,19 @@ def orth_flops(m, n, x):
     return (2 * x + 1) * m * n * n
 
 
+def orth_moved_bytes(m, n, x, precision):
+    """HBM bytes a CholQR3 call of x passes actually moves.  The one-block
+    FP64 route (n <= 16) recomputes the input of passes 2 and 3 from A and
+    writes only from pass 3 on (the first pass that can end the call), so
+    passes 1 and 2 read m n words and write none: (2x - 1) m n words for
+    x >= 3 instead of the (1 + 2x) m n of the algorithmic count.  Every
+    other route moves the algorithmic bytes."""
+    if precision == 0 and n <= 16:
+        words = 1 + sum(1 if k < 3 else 2 for k in range(1, x + 1))
+        return 8.0 * m * n * words
+    return orth_bytes(m, n, x)
+
+
 def append_bytes(m, q, p, x):
     return 8.0 * m * ((q + p) + x * (q + 2 * p))
 
@@ -298,7 +311,7 @@ def _orth_invariants(A, Q, R, m, n):
     return loo, math.sqrt(res / nrm)
 
 
-def _dominant_roofline(prof, m, n, precision):
+def _dominant_roofline(prof, m, n, precision, x=0):
     """Roofline object of the kernel kind with the larger total time among
     the timed launches: HBM bytes per launch below 80 columns, FP64 MFMA
     flops from 80 columns on (a pass moves 16 m n bytes for 2 m n^2 flops, so
@@ -335,10 +348,16 @@ def _dominant_roofline(prof, m, n, precision):
                 "kernel": names[kind], "launches": nl, "avg_launch_us": round(ms * 1e3 / nl, 2),
                 "algorithmic_flops_per_launch": float(fpl)}
     achieved = by / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[kind],
-            "launches": nl, "avg_launch_us": round(ms * 1e3 / nl, 2),
-            "algorithmic_bytes_per_launch": round(by / nl)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[kind],
+           "launches": nl, "avg_launch_us": round(ms * 1e3 / nl, 2),
+           "algorithmic_bytes_per_launch": round(by / nl)}
+    if precision == 0 and n <= 16 and kind == "apply" and x:
+        # passes 1 and 2 read A and write nothing (m n words, not 2 m n)
+        moved = sum(1 if k < 3 else 2 for k in range(1, x + 1)) / x * 8.0 * m * n
+        out["moved_bytes_per_launch"] = round(moved)
+        out["moved_GBs"] = round(moved * nl / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def orth_gpu(m, n, kappa, precision, steps, warmup, seed=(3,), A=None):
@@ -374,9 +393,10 @@ def orth_gpu(m, n, kappa, precision, steps, warmup, seed=(3,), A=None):
            "GFLOPs": round(orth_flops(m, n, x) / dt / 1e9, 1),
            "frac_of_hbm_peak": round(orth_bytes(m, n, x) / dt / 1e9 / HBM_PEAK_GBS, 4),
            "frac_of_fp64_mfma_peak": round(orth_flops(m, n, x) / dt / 1e12 / FP64_PEAK_TF, 4),
+           "moved_GBs": round(orth_moved_bytes(m, n, x, precision) / dt / 1e9, 1),
            "passes": x, "status": info["status"], "loo": loo, "rrr": rrr,
            "ok": info["status"] == 0 and loo <= 1e-12 and rrr <= 1e-13,
-           "roofline": _dominant_roofline(prof, m, n, precision)}
+           "roofline": _dominant_roofline(prof, m, n, precision, x)}
     del Q, R
     return res
 
