@@ -567,7 +567,7 @@ def main_orth(args):
         "config": {"workload": f"orth {args.m}x{args.n}, kappa {args.kappa:g}, "
                                f"{'mixed FP32/FP64' if args.precision else 'FP64'}",
                    "m": args.m, "n": args.n, "kappa": args.kappa, "precision": args.precision},
-        "GFLOPs": r["GFLOPs"], "roofline": r["roofline"], "passes": r["passes"],
+        "GFLOPs": r["GFLOPs"], "moved_GBs": r["moved_GBs"], "roofline": r["roofline"], "passes": r["passes"],
         "status": r["status"], "loo": r["loo"], "rrr": r["rrr"], "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
