@@ -56,12 +56,12 @@ def orth_flops(m, n, x):
 
 def orth_moved_bytes(m, n, x, precision):
     """HBM bytes a CholQR3 call of x passes actually moves.  The one-block
-    FP64 route (n <= 16) recomputes the input of passes 2 and 3 from A and
+    route (n <= 16, FP64 and mixed) recomputes the input of passes 2 and 3 from A and
     writes only from pass 3 on (the first pass that can end the call), so
     passes 1 and 2 read m n words and write none: (2x - 1) m n words for
     x >= 3 instead of the (1 + 2x) m n of the algorithmic count.  Every
     other route moves the algorithmic bytes."""
-    if precision == 0 and n <= 16:
+    if n <= 16:
         words = 1 + sum(1 if k < 3 else 2 for k in range(1, x + 1))
         return 8.0 * m * n * words
     return orth_bytes(m, n, x)
@@ -330,7 +330,7 @@ def _dominant_roofline(prof, m, n, precision, x=0):
         names, fused = {"apply": "block_pass apply", "gram": "block_pass Gram"}, True
     elif precision == 0 and n > 112:
         names, fused = {"apply": "wide_apply", "gram": "gram_pass"}, False
-    elif precision == 0 and n <= 16:
+    elif n <= 16:
         names, fused = {"apply": "narrow_pass (apply + Gramian)", "gram": "narrow_pass (Gramian)"}, True
     elif n <= 128:
         names, fused = {"apply": "wide_pass (apply + Gramian)", "gram": "wide_pass (Gramian)"}, True
@@ -352,7 +352,7 @@ def _dominant_roofline(prof, m, n, precision, x=0):
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[kind],
            "launches": nl, "avg_launch_us": round(ms * 1e3 / nl, 2),
            "algorithmic_bytes_per_launch": round(by / nl)}
-    if precision == 0 and n <= 16 and kind == "apply" and x:
+    if n <= 16 and kind == "apply" and x:
         # passes 1 and 2 read A and write nothing (m n words, not 2 m n)
         moved = sum(1 if k < 3 else 2 for k in range(1, x + 1)) / x * 8.0 * m * n
         out["moved_bytes_per_launch"] = round(moved)

@@ -241,9 +241,11 @@ const WideVariant kWide[] = {SQR_WIDE(1), SQR_WIDE(2), SQR_WIDE(3), SQR_WIDE(4),
 int g_wide_occ[2][2][kWideMax - kWideMin + 1];   // [fp32][apply][nb]
 
 // FP64 orth calls of one block (at most 16 columns): [Gram only, apply].
-const WideKernel kNarrow[2] = {narrow_pass<false>, narrow_pass<true>};
-const WideBatchKernel kNarrowB[2] = {narrow_pass_batch<false>, narrow_pass_batch<true>};
-int g_narrow_occ[2];
+const WideKernel kNarrow[2][2] = {{narrow_pass<false, false>, narrow_pass<true, false>},     // FP64 Gramian
+                                  {narrow_pass<false, true>, narrow_pass<true, true>}};      // FP32
+const WideBatchKernel kNarrowB[2][2] = {{narrow_pass_batch<false, false>, narrow_pass_batch<true, false>},
+                                        {narrow_pass_batch<false, true>, narrow_pass_batch<true, true>}};
+int g_narrow_occ[2];   // [apply]: the smaller of the two Gramian precisions
 
 // Orth calls of 8..16 blocks: a whole-pass apply and a Gramian kernel
 // (FP64, and FP32 for the mixed form).
@@ -388,10 +390,14 @@ void set_kernel_attributes_once() {
     g_split_occ[2][nb - kSplitMin] = n;
   }
   for (int ap = 0; ap < 2; ++ap) {
-    int n = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kNarrow[ap], kThreads, 0) != hipSuccess || n < 1)
-      n = 1;
-    g_narrow_occ[ap] = n;
+    g_narrow_occ[ap] = 1 << 30;
+    for (int g32 = 0; g32 < 2; ++g32) {
+      int n = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)kNarrow[g32][ap], kThreads, 0) != hipSuccess ||
+          n < 1)
+        n = 1;
+      g_narrow_occ[ap] = std::min(g_narrow_occ[ap], n);
+    }
   }
 }
 void set_kernel_attributes() { std::call_once(g_attr_once, set_kernel_attributes_once); }
@@ -542,9 +548,9 @@ struct Call {
 
 int variant_index(const Variant* v) { return (int)(v - kVariants); }
 
-// FP64 orthogonalisations of one block (at most 16 columns) run whole passes
-// in narrow_pass.
-bool narrow_route(const Call& c, int64_t P, bool mixed) { return c.mode == 0 && P == 1 && !mixed; }
+// Orthogonalisations of one block (at most 16 columns; FP64 or mixed) run
+// whole passes in narrow_pass.
+bool narrow_route(const Call& c, int64_t P, bool /*mixed*/) { return c.mode == 0 && P == 1; }
 // The first pass that can end the call (and so writes its result): the stop
 // test runs from pass min_passes on, the last pass is max_iter; at most
 // kNarrowSlots - 1, the passes whose input is recomputed from A.
@@ -894,8 +900,16 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     w.done = phase > 0 ? &b->ctrl->done : nullptr;
     w.passes = &b->ctrl->passes;
     w.copy_if_done = (phase == 1);
-    push_wide((const void*)kNarrow[apply ? 1 : 0], (const void*)kNarrowB[apply ? 1 : 0], w, nwg, kThreads, 0,
-              apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0), false);
+    // mixed form: phase 0 forms an FP32 Gramian; later phases launch both
+    // precisions and the one the device did not choose exits at once
+    bool join = false;
+    for (int g32 = mixed ? 1 : 0; g32 >= 0; --g32) {
+      if (mixed && phase == 0 && g32 == 0) break;
+      w.gram32 = (mixed && phase > 0) ? &b->ctrl->gram32 : nullptr;
+      push_wide((const void*)kNarrow[g32][apply ? 1 : 0], (const void*)kNarrowB[g32][apply ? 1 : 0], w, nwg,
+                kThreads, 0, apply ? 1 : 0, 8.0 * (double)b->m * (double)c.p * (apply ? 2.0 : 1.0), join);
+      join = true;
+    }
   } else if (c.mode == 0 && P <= kWideMax && (P >= 2 || mixed)) {
     // the whole pass in one launch (mixed form: one launch per Gramian
     // precision from pass 1 on; the one that does not match the device's

@@ -454,8 +454,8 @@ __device__ __forceinline__ int64_t e_off(int q16, int J) {
 }
 
 // ---------------------------------------------------------------------------
-// narrow_pass: one launch per pass of an FP64 orth call of at most 16
-// columns.  With one block the apply is Y = W D (D the inverse of R~, the
+// narrow_pass: one launch per pass of an orth call of at most 16
+// columns (G32: the mixed form's FP32 Gramian).  With one block the apply is Y = W D (D the inverse of R~, the
 // identity for the Gram-only pass) and the Gramian is Y^T Y.  The same
 // registers give both layouts without transposes: with lane (x, g), reg s
 // holding W[row x][col 4s + g] and D[4s + g][x],
@@ -469,9 +469,10 @@ __device__ __forceinline__ int64_t e_off(int q16, int J) {
 // ---------------------------------------------------------------------------
 constexpr int kNarrowPF = 4;
 
-template <bool APPLY>
+template <bool APPLY, bool G32>
 __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const int bid, const int nwg) {
   __shared__ double red[kWaves * 256];
+  if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = lane & 15, g = lane >> 4;
@@ -526,6 +527,7 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
   };
 
   d4 accg = d4{0.0, 0.0, 0.0, 0.0};
+  f4 accg32 = f4{0.f, 0.f, 0.f, 0.f};   // G32: Gramian of the FP32-rounded tiles
   const int64_t first = t0 + wave;
   if (first < t1) {
     d4 wb[kNarrowPF];
@@ -581,16 +583,26 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
             }
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) accg = mfma(ya[u], ya[u], accg);
+          for (int u = 0; u < 4; ++u) {
+            if (G32) {
+              const float yf = (float)ya[u];
+              accg32 = mfma32(yf, yf, accg32);
+            } else {
+              accg = mfma(ya[u], ya[u], accg);
+            }
+          }
         }
         load(tile + kWaves * kNarrowPF, wb[q], kb[q]);
       }
     }
   }
   // Gramian slot of the workgroup: element (i, j) at i * 16 + j, the wave
-  // partials added in wave order.
+  // partials added in wave order (in FP64 for both variants).
 #pragma unroll
-  for (int r = 0; r < 4; ++r) red[wave * 256 + (g + 4 * r) * 16 + x] = accg[r];
+  for (int r = 0; r < 4; ++r) {
+    if (G32) red[wave * 256 + (4 * g + r) * 16 + x] = (double)accg32[r];
+    else     red[wave * 256 + (g + 4 * r) * 16 + x] = accg[r];
+  }
   __syncthreads();
   double* out = a.part + (int64_t)bid * a.part_stride;
   for (int e = threadIdx.x; e < 256; e += kThreads) {
@@ -601,14 +613,14 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
   }
 }
 
-template <bool APPLY>
+template <bool APPLY, bool G32>
 __global__ __launch_bounds__(kThreads) void narrow_pass(WidePassArgs a) {
-  narrow_pass_body<APPLY>(a, blockIdx.x, gridDim.x);
+  narrow_pass_body<APPLY, G32>(a, blockIdx.x, gridDim.x);
 }
-template <bool APPLY>
+template <bool APPLY, bool G32>
 __global__ __launch_bounds__(kThreads) void narrow_pass_batch(BatchTable<WidePassArgs> t) {
   const int c = batch_call(t);
-  narrow_pass_body<APPLY>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
+  narrow_pass_body<APPLY, G32>(t.args[c], blockIdx.x - t.start[c], t.start[c + 1] - t.start[c]);
 }
 
 
