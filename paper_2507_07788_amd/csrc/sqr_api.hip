@@ -5,8 +5,9 @@
 // reduction of the per-workgroup partial Gramians (reduce_slots) and one
 // small_step.  The streaming kernels of a pass, by call and width (16-column
 // blocks P):
-//   orth, FP64, P = 1        narrow_pass (apply and Gramian in one launch)
-//   orth, P = 2..7 (mixed 1..8)  wide_pass (one launch per pass)
+//   orth, P = 1              narrow_pass (apply and Gramian in one launch;
+//                            FP32 Gramian variant for the mixed form)
+//   orth, P = 2..7 (mixed 2..8)  wide_pass (one launch per pass)
 //   orth, P = 8..16 (mixed 9..16)  wide_apply, then gram_pass (FP32 variant
 //                            for the mixed form's early passes)
 //   appends; orth, P > 16    block_pass, one launch per block

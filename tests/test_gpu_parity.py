@@ -179,6 +179,26 @@ def test_orth_deterministic():
     assert torch.equal(b1.q(), b2.q()) and torch.equal(b1.r(), b2.r())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n", [5, 16])
+def test_narrow_recomputed_passes_match_stored_passes(precision, n):
+    """At most 16 columns, the passes before the first one that can end the
+    call (min_passes = 3) recompute their input from A through the earlier
+    inverse factors and write nothing; with min_passes = 1 every pass writes
+    its result and the next reads it.  At kappa 1e10 the stopping test fails
+    after passes 1 and 2 either way, so both calls take the same passes on
+    the same values: Q and R are equal bit for bit."""
+    A = S.test_matrix(40000, n, 1e10, seed=(31, n))
+    Ad = dev(A)
+    b3, i3 = sq.sqr_orth(Ad, opts=sq.sqr_default_opts(precision=precision))
+    b1, i1 = sq.sqr_orth(Ad, opts=sq.sqr_default_opts(precision=precision, min_passes=1))
+    assert i3["status"] == 0 and i1["status"] == 0
+    assert i3["passes"] == i1["passes"] >= 3
+    assert torch.equal(b3.q(), b1.q()) and torch.equal(b3.r(), b1.r())
+    Qo, Ro, _ = O.orth(A)
+    _check_factors(A, host(b3.q()), host(b3.r()), Qo, Ro, 1e10)
+
+
 def test_orth_status_codes():
     A = S.test_matrix(400, 6, 1e2, seed=(13,))
     A[17, 3] = np.nan
