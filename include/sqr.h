@@ -122,6 +122,11 @@ void sqr_default_opts(sqr_opts* o);
  *            streams once `stream` is synchronised.  NULL: the call returns
  *            after enqueueing; sqr_last_info synchronises and reports.
  *
+ * Status: SQR_OK and SQR_NOT_CONVERGED leave the last pass's factors in Q
+ * and R.  After SQR_BREAKDOWN or SQR_ENONFINITE their contents are
+ * unspecified (with at most 16 columns, the passes before the first one
+ * that can end the call recompute their input from A and do not write Q).
+ *
  * Ownership: A, Q and R are borrowed and must stay allocated until the work
  * enqueued on `stream` completes.  The handle owns only its workspace.
  * Streams: a later call on the handle may use another stream; it first makes
