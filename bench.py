@@ -334,7 +334,7 @@ def _dominant_roofline(prof, m, n, precision, x=0):
     # fused: an apply launch also forms the next Gramian (2 m n^2 flops)
     if precision == 0 and n > 256:
         names, fused = {"apply": "block_pass apply", "gram": "block_pass Gram"}, True
-    elif precision == 0 and n > 112:
+    elif n > 112:
         names, fused = {"apply": "wide_apply", "gram": "gram_pass"}, False
     elif n <= 16:
         names, fused = {"apply": "narrow_pass (apply + Gramian)", "gram": "narrow_pass (Gramian)"}, True

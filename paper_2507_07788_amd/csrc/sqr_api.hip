@@ -7,9 +7,9 @@
 // blocks P):
 //   orth, P = 1              narrow_pass (apply and Gramian in one launch;
 //                            FP32 Gramian variant for the mixed form)
-//   orth, P = 2..7 (mixed 2..8)  wide_pass (one launch per pass)
-//   orth, P = 8..16 (mixed 9..16)  wide_apply, then gram_pass (FP32 variant
-//                            for the mixed form's early passes)
+//   orth, P = 2..7           wide_pass (one launch per pass)
+//   orth, P = 8..16          wide_apply, then gram_pass (FP32 variant for
+//                            the mixed form's early passes)
 //   appends; orth, P > 16    block_pass, one launch per block
 // The convergence decision is taken on the device; kernels of later passes
 // exit at once after it.  With a host `info` the driver enqueues the passes
@@ -838,7 +838,7 @@ int plan_pass(sqr_basis* b, const Call& c, int phase, std::vector<Launch>& out) 
     L.prof_kind = kind; L.prof_bytes = bytes; L.prof_join = join;
     out.push_back(L);
   };
-  if (c.mode == 0 && P >= kSplitMin && P <= kSplitMax && (!mixed || P > kWideMax)) {
+  if (c.mode == 0 && P >= kSplitMin && P <= kSplitMax) {
     // apply (from pass 1 on), then the Gramian of its result
     const int idx = (int)P - kSplitMin;
     const SplitVariant& sv = kSplit[idx];
