@@ -463,9 +463,10 @@ __device__ __forceinline__ int64_t e_off(int q16, int J) {
 //                                   (the A and B operand layout of Y^T Y),
 //   sum_s mfma(d_s, w_s) = D^T W^T, reg r = Y[row x][col g + 4r]
 //                                   (rows across lanes: coalesced stores).
-// Every wave works on its own row tiles (tile t0 + wave + 4k of the
-// workgroup's range) with kNarrowPF tiles in flight, and no barrier until
-// the four wave Gramians are summed in wave order into the workgroup's slot.
+// Steps of four row tiles are dealt round-robin over the grid, so that the
+// workgroups stream one common window of rows; every wave works on its own
+// tile of a step with kNarrowPF tiles in flight, and no barrier until the
+// four wave Gramians are summed in wave order into the workgroup's slot.
 // ---------------------------------------------------------------------------
 constexpr int kNarrowPF = 4;
 
@@ -477,13 +478,17 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
-  const int64_t per = (tiles + nwg - 1) / nwg;
-  const int64_t t0 = (int64_t)bid * per;
-  const int64_t t1 = min(tiles, t0 + per);
+  // steps of kWaves row tiles dealt round-robin over the grid: local step j
+  // is step j nwg + bid, and the wave takes row tile (j nwg + bid) kWaves + wave
+  const int64_t steps = (tiles + kWaves - 1) / kWaves;
+  const int64_t sw = steps > bid ? (steps - 1 - bid) / nwg + 1 : 0;
+  auto tile_of = [&](int64_t j) { return (j * nwg + bid) * kWaves + wave; };
 
   if (a.done && *a.done) {
     if (APPLY && a.copy_if_done && *a.passes == 0) {
-      for (int64_t t = t0 + wave; t < t1; t += kWaves) {
+      for (int64_t j = 0; j < sw; ++j) {
+        const int64_t t = tile_of(j);
+        if (t >= tiles) continue;
         const int64_t row = t * 16 + x;
         if (row >= a.m) continue;
         for (int c = g; c < a.n; c += 4)
@@ -508,13 +513,14 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
   }
 
   // W tile: reg r = W[row x][col g + 4r] as loaded; columns past n read
-  // zero (buffer range).  Rows past m and tiles past the range (t1) are
+  // zero (buffer range).  Rows past m and steps past the workgroup's last are
   // cleared by the mask `keep` when the tile is used, not at the load, so the
   // loads stay in flight until then.
   const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.win, ((int64_t)(a.n - 1) * a.ldw + a.m) * 8);
-  auto load = [&](int64_t tile, d4& w, uint64_t& keep) {
-    const int64_t row = min(tile, t1 - 1) * 16 + x;
-    keep = (row < a.m && tile < t1) ? ~0ull : 0ull;
+  auto load = [&](int64_t j, d4& w, uint64_t& keep) {
+    const int64_t tile = tile_of(j);
+    const int64_t row = min(tile, tiles - 1) * 16 + x;
+    keep = (row < a.m && tile < tiles && j < sw) ? ~0ull : 0ull;
     const int64_t rowc = row < a.m ? row : a.m - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -528,25 +534,25 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
 
   d4 accg = d4{0.0, 0.0, 0.0, 0.0};
   f4 accg32 = f4{0.f, 0.f, 0.f, 0.f};   // G32: Gramian of the FP32-rounded tiles
-  const int64_t first = t0 + wave;
-  if (first < t1) {
+  if (sw > 0) {
     d4 wb[kNarrowPF];
     uint64_t kb[kNarrowPF];
     // loads issued slot after slot (as in the loop), so that the waits at
     // the loop head are counted per slot
 #pragma unroll
     for (int q = 0; q < kNarrowPF; ++q) {
-      load(first + kWaves * q, wb[q], kb[q]);
+      load(q, wb[q], kb[q]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    for (int64_t k0 = 0; first + kWaves * k0 < t1; k0 += kNarrowPF) {
+    for (int64_t k0 = 0; k0 < sw; k0 += kNarrowPF) {
 #pragma unroll
       for (int q = 0; q < kNarrowPF; ++q) {
-        // wb[q] is used first and then refilled with the tile kNarrowPF
-        // steps ahead: the load lands in the same registers, so no copy (and
+        // wb[q] is used first and then refilled with the wave's tile
+        // kNarrowPF local steps ahead: the load lands in the same registers, so no copy (and
         // no wait for the loads in flight) is needed at the loop's end.  A
         // tile past the range holds zeros: no branch around the arithmetic.
-        const int64_t tile = first + kWaves * (k0 + q);
+        const int64_t tile = tile_of(k0 + q);
+        const bool tile_ok = k0 + q < sw && tile < tiles;
         __builtin_amdgcn_sched_barrier(0);   // keep this slot's wait here, not hoisted
         d4 w;
 #pragma unroll
@@ -574,7 +580,7 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) yb = mfma(dv[s4], w[s4], yb);
             const int64_t row = tile * 16 + x;
-            if (tile < t1 && row < a.m) {
+            if (tile_ok && row < a.m) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int col = g + 4 * r;
@@ -592,7 +598,7 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
             }
           }
         }
-        load(tile + kWaves * kNarrowPF, wb[q], kb[q]);
+        load(k0 + q + kNarrowPF, wb[q], kb[q]);
       }
     }
   }
@@ -631,7 +637,8 @@ __global__ __launch_bounds__(kThreads) void narrow_pass_batch(BatchTable<WidePas
 // keeps the Y blocks of its 16-row tile in registers, so the prefix Y_<J is
 // never re-read from HBM: the pass reads W once and writes Y once.
 //
-// Workgroup: four waves, one 16-row tile each (64 rows per step).  LDS holds
+// Workgroup: four waves, one 16-row tile each (64 rows per step; steps dealt
+// round-robin over the grid).  LDS holds
 // the operands of the pass (per block J the panel [C_J; D_J], row-major, 16
 // columns) and, per step, the transposed Y tiles of all four waves in MFMA
 // operand order; each wave then accumulates the Gramian blocks (I, J) it
@@ -651,14 +658,16 @@ __device__ __forceinline__ void wide_pass_body(const WidePassArgs& a, const int 
   const int x = lane & 15, g = lane >> 4;
   const int64_t tiles = (a.m + 15) / 16;
   const int64_t steps = (tiles + kWaves - 1) / kWaves;
-  const int64_t per = (steps + nwg - 1) / nwg;
-  const int64_t s0 = (int64_t)bid * per;
-  const int64_t s1 = min(steps, s0 + per);
+  // steps dealt round-robin over the grid: local step i is step i nwg + bid
+  const int64_t sw = steps > bid ? (steps - 1 - bid) / nwg + 1 : 0;
+  auto step_of = [&](int64_t i) { return i * nwg + bid; };
 
   if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
   if (a.done && *a.done) {
     if (APPLY && a.copy_if_done && *a.passes == 0) {
-      for (int64_t t = s0 * kWaves + wave; t < min(tiles, s1 * kWaves); t += kWaves) {
+      for (int64_t i = 0; i < sw; ++i) {
+        const int64_t t = step_of(i) * kWaves + wave;
+        if (t >= tiles) continue;
         const int64_t row = t * 16 + x;
         if (row >= a.m) continue;
         for (int c = g; c < a.n; c += 4)
@@ -719,17 +728,17 @@ __device__ __forceinline__ void wide_pass_body(const WidePassArgs& a, const int 
   }
 
   d4 wnext[NB];
-  load_w(min(s0 * kWaves + wave, tiles - 1), wnext);
+  load_w(min(step_of(0) * kWaves + wave, tiles - 1), wnext);
   __syncthreads();  // panels loaded
   double* myop = op + wave * NB * 4 * kOpSlot;
-  for (int64_t s = s0; s < s1; ++s) {
-    const int64_t tile = s * kWaves + wave;
+  for (int64_t i = 0; i < sw; ++i) {
+    const int64_t tile = step_of(i) * kWaves + wave;
     const int64_t row = tile * 16 + x;
     const bool row_ok = tile < tiles && row < a.m;
     d4 y[NB];
 #pragma unroll
     for (int J = 0; J < NB; ++J) y[J] = wnext[J];
-    load_w(min(tile + kWaves, tiles - 1), wnext);
+    load_w(min(step_of(i + 1) * kWaves + wave, tiles - 1), wnext);
     if (!APPLY && !row_ok) {
 #pragma unroll
       for (int J = 0; J < NB; ++J) y[J] = d4{0.0, 0.0, 0.0, 0.0};
