@@ -455,14 +455,17 @@ __device__ __forceinline__ int64_t e_off(int q16, int J) {
 
 // ---------------------------------------------------------------------------
 // narrow_pass: one launch per pass of an orth call of at most 16
-// columns (G32: the mixed form's FP32 Gramian).  With one block the apply is Y = W D (D the inverse of R~, the
-// identity for the Gram-only pass) and the Gramian is Y^T Y.  The same
-// registers give both layouts without transposes: with lane (x, g), reg s
-// holding W[row x][col 4s + g] and D[4s + g][x],
+// columns (G32: the mixed form's FP32 Gramian).  With one block the apply is Y = W D (D the inverse of R~;
+// none in the Gram-only pass) and the Gramian is Y^T Y.  With lane (x, g),
+// reg s holding W[row x][col 4s + g] (as loaded) and D[4s + g][x],
 //   sum_s mfma(w_s, d_s) = W D,     reg r = Y[row g + 4r][col x]
 //                                   (the A and B operand layout of Y^T Y),
 //   sum_s mfma(d_s, w_s) = D^T W^T, reg r = Y[row x][col g + 4r]
-//                                   (rows across lanes: coalesced stores).
+//                                   (the load layout: the earlier factors of
+//                                   a recomputed pass).
+// The Gram-only pass brings W into the operand layout, and a storing pass
+// brings Y back to rows across lanes (coalesced stores), through a
+// wave-private 16 x 16 LDS tile rather than a product with I.
 // Steps of four row tiles are dealt round-robin over the grid, so that the
 // workgroups stream one common window of rows; every wave works on its own
 // tile of a step with kNarrowPF tiles in flight, and no barrier until the
@@ -473,6 +476,7 @@ constexpr int kNarrowPF = 4;
 template <bool APPLY, bool G32>
 __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const int bid, const int nwg) {
   __shared__ double red[kWaves * 256];
+  __shared__ double trs[kWaves * 16 * kYPitch];   // one 16 x 16 tile per wave
   if (a.gram32 && *a.gram32 != (G32 ? 1 : 0)) return;   // the other variant's pass
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -500,13 +504,13 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
 
   // The apply multiplies the input by the inverse factors of `levels`
   // passes in turn (a pass that recomputes its input from A); dv is the last
-  // one (the identity in the Gram-only pass, which only transposes), dp[l]
-  // the earlier ones.  k-slice s of a factor is read as D[4s + g][x].
+  // one (unused in the Gram-only pass), dp[l] the earlier ones.  k-slice s
+  // of a factor is read as D[4s + g][x].
   const int lv = APPLY ? a.levels : 1;   // 1 .. kNarrowSlots - 1
   double dv[4], dp[kNarrowSlots - 2][4];
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
-    dv[s4] = APPLY ? a.rinv[(lv - 1) * 256 + (4 * s4 + g) * 16 + x] : ((4 * s4 + g == x) ? 1.0 : 0.0);
+    dv[s4] = APPLY ? a.rinv[(lv - 1) * 256 + (4 * s4 + g) * 16 + x] : 0.0;
 #pragma unroll
     for (int l = 0; l < kNarrowSlots - 2; ++l)
       dp[l][s4] = (APPLY && l + 1 < lv) ? a.rinv[l * 256 + (4 * s4 + g) * 16 + x] : 0.0;
@@ -573,12 +577,31 @@ __device__ __forceinline__ void narrow_pass_body(const WidePassArgs& a, const in
         }
         {
           d4 ya = d4{0.0, 0.0, 0.0, 0.0};
+          if (!APPLY) {
+            // Gram-only pass: the tile in the Gramian's operand layout
+            // through the wave's LDS tile instead of a product with I
+            double* tr = trs + wave * 16 * kYPitch;
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) ya = mfma(w[s4], dv[s4], ya);
+            for (int r = 0; r < 4; ++r) tr[x * kYPitch + g + 4 * r] = w[r];
+            wave_lds_order();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ya[r] = tr[(g + 4 * r) * kYPitch + x];
+            wave_lds_order();
+          } else {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) ya = mfma(w[s4], dv[s4], ya);
+          }
           if (APPLY && a.store) {
-            d4 yb = d4{0.0, 0.0, 0.0, 0.0};
+            // rows across lanes through the wave's LDS tile (ya register r is
+            // row g + 4r of column x; yb register r is column g + 4r of row x)
+            double* tr = trs + wave * 16 * kYPitch;
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) yb = mfma(dv[s4], w[s4], yb);
+            for (int r = 0; r < 4; ++r) tr[(g + 4 * r) * kYPitch + x] = ya[r];
+            wave_lds_order();
+            d4 yb;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yb[r] = tr[x * kYPitch + g + 4 * r];
+            wave_lds_order();
             const int64_t row = tile * 16 + x;
             if (tile_ok && row < a.m) {
 #pragma unroll
