@@ -900,6 +900,40 @@ def test_orth_full_size_m4e6_n64_against_oracle():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("precision", [0, 1])
+def test_orth_full_size_m4e6_n16_against_oracle(precision):
+    """m = 4e6, n = 16, kappa = 1e4: the one-block route at its full launch
+    shape (passes 1 and 2 recompute their input from A, 64-row steps dealt
+    over the whole grid); R and sampled rows of Q against the oracle at full
+    size, FP64 and the mixed form."""
+    A = S.test_matrix(4_000_000, 16, 1e4, seed=(3,))
+    Qo, Ro, io = O.orth(A)
+    print(f"orth 4e6 x 16, precision {precision}", flush=True)
+    b, info = sq.sqr_orth(dev(A), opts=sq.sqr_default_opts(precision=precision))
+    assert info["status"] == 0 and abs(info["passes"] - io["passes"]) <= 1
+    Rg = host(b.r())
+    assert np.max(np.abs(Rg - Ro)) <= 1e-10 * 1e4 * np.max(np.abs(Ro))
+    rows = np.random.default_rng(1).choice(A.shape[0], 4000, replace=False)
+    Qg = b.q()[torch.as_tensor(rows, device=b.Q.device)].cpu().numpy()
+    assert np.max(np.abs(Qg - Qo[rows])) <= 1e-10 * 1e4 * np.max(np.abs(Qo[rows]))
+    loo, rrr = _invariants_dev(dev(A), b.Q, b.R, 16)
+    assert loo <= 1e-12 and rrr <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(1_000_003, 16), (1_000_003, 11), (262_147, 40), (65_541, 16)])
+def test_orth_ragged_row_steps_against_oracle(m, n):
+    """Row counts whose 64-row steps do not divide evenly over the grid and
+    whose last step and last tile are partial: every row enters the Gramian
+    and the result once (one-block route for n <= 16, fused wide route at 40)."""
+    A = S.test_matrix(m, n, 1e6, seed=(5,))
+    Qo, Ro, io = O.orth(A)
+    print(f"orth {m} x {n}", flush=True)
+    b, info = sq.sqr_orth(dev(A))
+    assert info["status"] == 0 and abs(info["passes"] - io["passes"]) <= 1
+    _check_factors(A, host(b.q()), host(b.r()), Qo, Ro, 1e6)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [0, 1])
 def test_orth_full_size_m4e6_n128_kappa1e12(precision):
     A = S.test_matrix_device(4_000_000, 128, 1e12, (3,))
     b, info = sq.sqr_orth(A, opts=sq.sqr_default_opts(precision=precision))
