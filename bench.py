@@ -517,7 +517,9 @@ def main_growth(args):
             import synth
             A = synth.test_matrix_device(4_000_000, n, 1e4, (3,))
             for prec in (0, 1):
-                r = orth_gpu(4_000_000, n, 1e4, prec, steps=5, warmup=2, A=A)
+                # 20 timed calls below 1 ms per call keep the events of the last
+                # one and the spread between calls from moving the mean
+                r = orth_gpu(4_000_000, n, 1e4, prec, steps=20 if n <= 64 else 5, warmup=3, A=A)
                 subs[f"C3_orth_4e6x{n}_k1e4_{'mixed' if prec else 'fp64'}"] = r
                 log(f"sub C3 n={n} prec={prec}: {r['ms']} ms")
             f64 = subs[f"C3_orth_4e6x{n}_k1e4_fp64"]
