@@ -1141,7 +1141,7 @@ int launch_gram(sqr_basis* b, const Call& c, int phase, hipStream_t s) {
   return exec_single(b, phase, L, s);
 }
 
-int fetch(sqr_basis* b, hipStream_t s) {
+int fetch(sqr_basis* /*b*/, hipStream_t s) {
   if (hipStreamSynchronize(s) != hipSuccess) return SQR_EHIP;
   return SQR_OK;
 }
